@@ -1,0 +1,341 @@
+"""Seeded synthetic text for tests and benchmarks.
+
+Holds none of the transcoding arithmetic: characters are drawn as code points
+from fixed ranges (each range has a known UTF-8 length class), and encoded to
+UTF-8 / UTF-16LE with CPython's built-in codecs. Both the GPU parity tests and
+the CPU oracle consume what this module produces; expected results always come
+from the oracle, never from here.
+
+The profiles stand in for the paper's data files (section 6.3, Table "data"),
+which are not available: their per-length character mixes follow that table
+(Latin ~ lipsum Latin / English, Cyrillic ~ lipsum and Mars Russian, CJK ~
+lipsum Chinese / Japanese, Emoji ~ lipsum Emoji).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+BASE_SEED = 210910433
+MIB = 1 << 20
+
+_ASCII_PRINTABLE = np.arange(0x20, 0x7F, dtype=np.uint32)
+_ASCII_SPACE_PUNCT = np.array([ord(c) for c in " ,.;:!?-'\"()"], dtype=np.uint32)
+
+
+@dataclass(frozen=True)
+class CharClass:
+    prob: float
+    utf8_len: int          # by construction of the ranges below
+    ranges: tuple          # inclusive (lo, hi) code point ranges, drawn uniformly over their union
+    alphabet: tuple = ()   # explicit list instead of ranges
+
+
+def _cls(prob, utf8_len, *ranges):
+    return CharClass(prob, utf8_len, tuple(ranges))
+
+
+PROFILES = {
+    # 70/10/15/5 % of characters by encoded length, uniform within each range
+    "mix": (
+        _cls(0.70, 1, (0x20, 0x7E)),
+        _cls(0.10, 2, (0x80, 0x7FF)),
+        _cls(0.15, 3, (0x800, 0xD7FF), (0xE000, 0xFFFF)),
+        _cls(0.05, 4, (0x10000, 0x10FFFF)),
+    ),
+    "latin": (
+        _cls(0.98, 1, (0x20, 0x7E)),
+        _cls(0.02, 2, (0xC0, 0x17F)),
+    ),
+    "cyrillic": (
+        CharClass(0.45, 1, (), tuple(int(c) for c in _ASCII_SPACE_PUNCT)),
+        _cls(0.55, 2, (0x400, 0x4FF)),
+    ),
+    "cjk": (
+        _cls(0.10, 1, (0x20, 0x7E)),
+        _cls(0.90, 3, (0x4E00, 0x9FFF)),
+    ),
+    "emoji": (
+        _cls(0.10, 1, (0x20, 0x7E)),
+        _cls(0.90, 4, (0x1F300, 0x1FAFF)),
+    ),
+}
+LARGE_PROFILES = ("latin", "cyrillic", "cjk", "emoji")
+BATCH_PROFILES = ("mix", "latin", "cyrillic", "cjk", "emoji")
+
+# error kinds injected into UTF-8 text (names match the library's error kinds)
+UTF8_ERROR_KINDS = ("OVERLONG", "SURROGATE", "TOO_LARGE", "TRUNCATED", "STRAY_CONTINUATION", "BAD_LEAD")
+
+
+def rng_for(*key) -> np.random.Generator:
+    """PCG64 stream for a (config, purpose, ...) key under the base seed."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([BASE_SEED, *[hash_key(k) for k in key]])))
+
+
+def hash_key(k) -> int:
+    if isinstance(k, int):
+        return k & 0xFFFFFFFF
+    h = 2166136261
+    for ch in str(k).encode():
+        h = ((h ^ ch) * 16777619) & 0xFFFFFFFF
+    return h
+
+
+def _draw_class(rng, cc: CharClass, n: int) -> np.ndarray:
+    if cc.alphabet:
+        alpha = np.asarray(cc.alphabet, dtype=np.uint32)
+        return alpha[rng.integers(0, alpha.size, size=n)]
+    sizes = np.array([hi - lo + 1 for lo, hi in cc.ranges], dtype=np.int64)
+    k = rng.integers(0, int(sizes.sum()), size=n, dtype=np.int64)
+    out = np.empty(n, dtype=np.uint32)
+    base = 0
+    remaining = np.ones(n, dtype=bool)
+    for (lo, hi), sz in zip(cc.ranges, sizes):
+        sel = remaining & (k < base + sz)
+        out[sel] = lo + (k[sel] - base)
+        remaining &= ~sel
+        base += sz
+    return out
+
+
+@dataclass
+class Text:
+    """A synthetic text: code points plus their encodings (CPython codecs)."""
+    cps: np.ndarray        # uint32 code points
+    utf8_len: np.ndarray   # uint8 per character (by construction)
+    u8: np.ndarray         # uint8 UTF-8 bytes
+    u16: np.ndarray        # uint16 UTF-16LE code units
+
+    @property
+    def char_starts_u8(self) -> np.ndarray:
+        """Byte offset of every character (plus the end)."""
+        return np.concatenate([[0], np.cumsum(self.utf8_len, dtype=np.int64)])
+
+    @property
+    def char_starts_u16(self) -> np.ndarray:
+        """Word offset of every character (plus the end); 4-byte UTF-8 characters are pairs."""
+        return np.concatenate([[0], np.cumsum(1 + (self.utf8_len == 4), dtype=np.int64)])
+
+
+def encode_utf8(cps: np.ndarray) -> np.ndarray:
+    s = np.ascontiguousarray(cps, dtype="<u4").tobytes().decode("utf-32-le")
+    return np.frombuffer(s.encode("utf-8"), dtype=np.uint8)
+
+
+def encode_utf16le(cps: np.ndarray) -> np.ndarray:
+    s = np.ascontiguousarray(cps, dtype="<u4").tobytes().decode("utf-32-le")
+    return np.frombuffer(s.encode("utf-16-le"), dtype="<u2")
+
+
+def make_text(profile: str, n_bytes: int, rng: np.random.Generator, encode16: bool = True) -> Text:
+    """Text of exactly ``n_bytes`` UTF-8 bytes: characters drawn from the profile,
+    cut at the last whole character and padded with U+0020."""
+    classes = PROFILES[profile]
+    probs = np.array([c.prob for c in classes])
+    probs = probs / probs.sum()
+    lens = np.array([c.utf8_len for c in classes], dtype=np.uint8)
+    mean = float((probs * lens).sum())
+    cps_parts, len_parts, total = [], [], 0
+    while total < n_bytes:
+        m = int((n_bytes - total) / mean * 1.01) + 16
+        cls = rng.choice(len(classes), size=m, p=probs)
+        cps = np.empty(m, dtype=np.uint32)
+        for i, cc in enumerate(classes):
+            sel = cls == i
+            cps[sel] = _draw_class(rng, cc, int(sel.sum()))
+        cps_parts.append(cps)
+        len_parts.append(lens[cls])
+        total += int(lens[cls].sum(dtype=np.int64))
+    cps = np.concatenate(cps_parts)
+    clen = np.concatenate(len_parts)
+    cum = np.cumsum(clen, dtype=np.int64)
+    k = int(np.searchsorted(cum, n_bytes, side="right"))
+    used = int(cum[k - 1]) if k else 0
+    pad = n_bytes - used
+    cps = np.concatenate([cps[:k], np.full(pad, 0x20, dtype=np.uint32)])
+    clen = np.concatenate([clen[:k], np.ones(pad, dtype=np.uint8)])
+    u8 = encode_utf8(cps)
+    assert u8.size == n_bytes
+    u16 = encode_utf16le(cps) if encode16 else np.zeros(0, dtype=np.uint16)
+    return Text(cps, clen, u8, u16)
+
+
+# ---------------------------------------------------------------- error injection
+
+def _cont(rng, lo=0x80, hi=0xBF, n=1):
+    return [int(x) for x in rng.integers(lo, hi + 1, size=n)]
+
+
+def utf8_error_sequence(kind: str, rng: np.random.Generator) -> list:
+    """A short ill-formed byte sequence of the named kind (the kind that the
+    first-error rules assign is checked against the oracle by the tests)."""
+    if kind == "OVERLONG":
+        v = int(rng.integers(0, 3))
+        if v == 0:
+            return [int(rng.integers(0xC0, 0xC2))] + _cont(rng)
+        if v == 1:
+            return [0xE0] + _cont(rng, 0x80, 0x9F) + _cont(rng)
+        return [0xF0] + _cont(rng, 0x80, 0x8F) + _cont(rng, n=2)
+    if kind == "SURROGATE":
+        return [0xED] + _cont(rng, 0xA0, 0xBF) + _cont(rng)
+    if kind == "TOO_LARGE":
+        if rng.integers(0, 2) == 0:
+            return [0xF4] + _cont(rng, 0x90, 0xBF) + _cont(rng, n=2)
+        return [int(rng.integers(0xF5, 0xF8))] + _cont(rng, n=3)
+    if kind == "TRUNCATED":
+        ln = int(rng.integers(2, 5))
+        seq = encode_utf8(np.array([{2: 0x4A9, 3: 0x6F22, 4: 0x1F600}[ln]], dtype=np.uint32)).tolist()
+        return seq[: int(rng.integers(1, ln))]
+    if kind == "STRAY_CONTINUATION":
+        return _cont(rng)
+    if kind == "BAD_LEAD":
+        return [int(rng.integers(0xF8, 0x100))]
+    raise ValueError(kind)
+
+
+def inject_utf8_error(u8: np.ndarray, char_starts: np.ndarray, kind: str, rng: np.random.Generator,
+                      position: int | None = None):
+    """Copy of ``u8`` (same length) with an ill-formed sequence written at a
+    character boundary. Continuation bytes left over from overwritten characters
+    are replaced by U+0020 so that the injected sequence is what it claims.
+    Returns (bytes, boundary position used)."""
+    seq = utf8_error_sequence(kind, rng)
+    n = u8.size
+    starts = char_starts[:-1]
+    starts = starts[starts + len(seq) + 1 <= n]
+    if position is None:
+        position = int(starts[rng.integers(0, starts.size)])
+    out = u8.copy()
+    out[position:position + len(seq)] = seq
+    j = position + len(seq)
+    while j < n and (out[j] & 0xC0) == 0x80:
+        out[j] = 0x20
+        j += 1
+    return out, position
+
+
+def inject_utf16_error(u16: np.ndarray, char_starts: np.ndarray, rng: np.random.Generator,
+                       position: int | None = None):
+    """Copy of ``u16`` with a lone high surrogate (followed by a non-low word) or
+    a lone low surrogate (not preceded by a high word) at a character boundary.
+    Returns (words, word index used)."""
+    out = u16.copy()
+    n = u16.size
+    starts = char_starts[:-1]
+    if position is None:
+        position = int(starts[rng.integers(0, starts.size)])
+    high = bool(rng.integers(0, 2))
+    if high:
+        out[position] = int(rng.integers(0xD800, 0xDC00))
+        if position + 1 < n and 0xDC00 <= out[position + 1] <= 0xDFFF:
+            out[position + 1] = 0x20
+    else:
+        # overwrite a whole character so no high word precedes the low one
+        out[position] = int(rng.integers(0xDC00, 0xE000))
+        if position + 1 < n and 0xDC00 <= out[position + 1] <= 0xDFFF:
+            out[position + 1] = 0x20
+    return out, position
+
+
+# ---------------------------------------------------------------- configurations
+
+def single_buffer(n_bytes: int = MIB, profile: str = "mix", seed_key="cfg1") -> Text:
+    """One buffer of exactly n_bytes UTF-8 (default: the 1 MiB mixed buffer)."""
+    return make_text(profile, n_bytes, rng_for(seed_key, profile, n_bytes))
+
+
+def single_buffer_with_errors(text: Text, seed_key="cfg1-errors"):
+    """One copy per UTF-8 error kind: list of (kind, bytes, injected position)."""
+    rng = rng_for(seed_key, text.u8.size)
+    starts = text.char_starts_u8
+    out = []
+    for kind in UTF8_ERROR_KINDS:
+        b, pos = inject_utf8_error(text.u8, starts, kind, rng)
+        out.append((kind, b, pos))
+    return out
+
+
+def large_profile(profile: str, n_bytes: int = 256 * MIB) -> Text:
+    return make_text(profile, n_bytes, rng_for("cfg2", profile, n_bytes))
+
+
+@dataclass
+class DocBatch:
+    data: np.ndarray        # concatenated documents (uint8 for UTF-8, uint16 for UTF-16LE)
+    offsets: np.ndarray     # int64, n_docs + 1, in input units
+    profiles: np.ndarray    # profile index per document (into BATCH_PROFILES)
+    injected: np.ndarray    # bool per document: carries an injected error
+
+
+def _lognormal_lengths(rng, n, median, sigma, lo, hi):
+    x = np.exp(np.log(median) + sigma * rng.standard_normal(n))
+    return np.clip(np.round(x), lo, hi).astype(np.int64)
+
+
+def utf8_documents(n_docs: int = 100_000, median: int = 2048, sigma: float = 1.5,
+                   lo: int = 16, hi: int = MIB, error_frac: float = 0.01,
+                   pool_bytes: int | None = None, seed_key="cfg3") -> DocBatch:
+    """Many UTF-8 documents with log-normal byte lengths, each a character-
+    aligned slice of one profile's text pool; a fraction carry one injected
+    error of a uniformly drawn kind."""
+    rng = rng_for(seed_key, n_docs)
+    want = _lognormal_lengths(rng, n_docs, median, sigma, lo, hi)
+    prof = rng.integers(0, len(BATCH_PROFILES), size=n_docs)
+    if pool_bytes is None:
+        pool_bytes = int(min(max(4 * hi, 2 * want.sum() // len(BATCH_PROFILES)), 256 * MIB))
+    pools = [make_text(p, pool_bytes, rng_for(seed_key, "pool", p, pool_bytes), encode16=False)
+             for p in BATCH_PROFILES]
+    pool_starts = [t.char_starts_u8 for t in pools]
+    parts, lens = [], np.zeros(n_docs, dtype=np.int64)
+    inj = rng.random(n_docs) < error_frac
+    for d in range(n_docs):
+        t, cs = pools[prof[d]], pool_starts[prof[d]]
+        max_start = cs.size - 1
+        i = int(rng.integers(0, max_start))
+        b0 = int(cs[i])
+        j = int(np.searchsorted(cs, b0 + want[d], side="right")) - 1
+        j = max(j, i)
+        doc = t.u8[b0:int(cs[j])]
+        if inj[d] and doc.size >= 8:
+            kind = UTF8_ERROR_KINDS[int(rng.integers(0, len(UTF8_ERROR_KINDS)))]
+            doc, _ = inject_utf8_error(doc, cs[i:j + 1] - b0, kind, rng)
+        else:
+            inj[d] = False
+        parts.append(doc)
+        lens[d] = doc.size
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    return DocBatch(np.concatenate(parts) if parts else np.zeros(0, np.uint8), offsets, prof, inj)
+
+
+def utf16_documents(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 * MIB,
+                    error_frac: float = 0.005, pool_bytes: int | None = None, seed_key="cfg4") -> DocBatch:
+    """Many UTF-16LE documents with byte lengths uniform in [lo, hi] (even),
+    character-aligned slices of per-profile pools; a fraction carry one
+    unpaired surrogate."""
+    rng = rng_for(seed_key, n_docs)
+    want_words = rng.integers(lo_bytes // 2, hi_bytes // 2 + 1, size=n_docs)
+    prof = rng.integers(0, len(BATCH_PROFILES), size=n_docs)
+    if pool_bytes is None:
+        pool_bytes = int(min(max(2 * hi_bytes, want_words.sum()), 128 * MIB))
+    pools = [make_text(p, pool_bytes, rng_for(seed_key, "pool", p, pool_bytes)) for p in BATCH_PROFILES]
+    pool_starts = [t.char_starts_u16 for t in pools]
+    parts, lens = [], np.zeros(n_docs, dtype=np.int64)
+    inj = rng.random(n_docs) < error_frac
+    for d in range(n_docs):
+        t, cs = pools[prof[d]], pool_starts[prof[d]]
+        total = int(cs[-1])
+        w = int(min(want_words[d], total))
+        i = int(rng.integers(0, max(1, int(np.searchsorted(cs, total - w, side="right")))))
+        b0 = int(cs[i])
+        j = int(np.searchsorted(cs, b0 + w, side="right")) - 1
+        j = max(j, i)
+        doc = t.u16[b0:int(cs[j])]
+        if inj[d] and doc.size >= 4:
+            doc, _ = inject_utf16_error(doc, cs[i:j + 1] - b0, rng)
+        else:
+            inj[d] = False
+        parts.append(doc)
+        lens[d] = doc.size
+    offsets = np.concatenate([[0], np.cumsum(lens)])
+    return DocBatch(np.concatenate(parts) if parts else np.zeros(0, np.uint16), offsets, prof, inj)

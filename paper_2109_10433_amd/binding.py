@@ -1,0 +1,186 @@
+"""ctypes binding to libhiputf.so (C ABI in include/hiputf.h).
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of the transcoding runs in the library's gfx950 kernels.
+There is no fallback: importing this module without the built library, or
+calling it on CPU tensors, raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import NamedTuple
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhiputf.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2109_10433_amd.build`")
+
+OK = 0
+BAD_LEAD = 1
+TRUNCATED = 2
+STRAY_CONTINUATION = 3
+OVERLONG = 4
+TOO_LARGE = 5
+SURROGATE = 6
+UNPAIRED_SURROGATE = 7
+OUTPUT_TOO_SMALL = 16
+INVALID_ARGUMENT = 17
+DEVICE = 18
+
+OP_VALIDATE_UTF8 = 0
+OP_UTF16_LENGTH_FROM_UTF8 = 1
+OP_CONVERT_UTF8_TO_UTF16LE = 2
+OP_VALIDATE_UTF16LE = 3
+OP_UTF8_LENGTH_FROM_UTF16LE = 4
+OP_CONVERT_UTF16LE_TO_UTF8 = 5
+
+
+class HuResult(ctypes.Structure):
+    _fields_ = [("error", ctypes.c_int32), ("reserved", ctypes.c_int32), ("count", ctypes.c_uint64)]
+
+
+class Result(NamedTuple):
+    error: int
+    count: int
+
+
+lib = ctypes.CDLL(LIB_PATH)
+_p, _sz, _i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+for _name, _args in [
+    ("validate_utf8", [_p, _sz, _p]),
+    ("utf16_length_from_utf8", [_p, _sz, _p]),
+    ("convert_utf8_to_utf16le", [_p, _sz, _p, _sz, _p]),
+    ("validate_utf16le", [_p, _sz, _p]),
+    ("utf8_length_from_utf16le", [_p, _sz, _p]),
+    ("convert_utf16le_to_utf8", [_p, _sz, _p, _sz, _p]),
+]:
+    getattr(lib, _name).argtypes = _args
+    getattr(lib, _name).restype = HuResult
+for _name, _args in [
+    ("validate_utf8_async", [_p, _sz, _p, _p, _sz, _p]),
+    ("utf16_length_from_utf8_async", [_p, _sz, _p, _p, _sz, _p]),
+    ("convert_utf8_to_utf16le_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+    ("validate_utf16le_async", [_p, _sz, _p, _p, _sz, _p]),
+    ("utf8_length_from_utf16le_async", [_p, _sz, _p, _p, _sz, _p]),
+    ("convert_utf16le_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+]:
+    getattr(lib, _name).argtypes = _args
+    getattr(lib, _name).restype = _i
+lib.hu_workspace_bytes.argtypes = [_i, _sz]
+lib.hu_workspace_bytes.restype = _sz
+lib.hu_workspace_init.argtypes = [_p, _sz, _p]
+lib.hu_workspace_init.restype = _i
+lib.hu_error_name.argtypes = [_i]
+lib.hu_error_name.restype = ctypes.c_char_p
+lib.hu_shutdown.argtypes = []
+lib.hu_shutdown.restype = None
+
+EXPORTED = [
+    "validate_utf8", "utf16_length_from_utf8", "convert_utf8_to_utf16le",
+    "validate_utf16le", "utf8_length_from_utf16le", "convert_utf16le_to_utf8",
+    "validate_utf8_async", "utf16_length_from_utf8_async", "convert_utf8_to_utf16le_async",
+    "validate_utf16le_async", "utf8_length_from_utf16le_async", "convert_utf16le_to_utf8_async",
+    "hu_workspace_bytes", "hu_workspace_init", "hu_error_name", "hu_shutdown",
+]
+
+
+def error_name(code: int) -> str:
+    return lib.hu_error_name(int(code)).decode()
+
+
+def stream_handle(stream: torch.cuda.Stream | None = None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(t: torch.Tensor, dtypes, what: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{what} must have dtype in {dtypes}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+_U8 = (torch.uint8,)
+_U16 = (torch.int16, torch.uint16)
+
+
+def _res(r: HuResult) -> Result:
+    return Result(int(r.error), int(r.count))
+
+
+def validate_utf8(src: torch.Tensor, stream=None) -> Result:
+    _check(src, _U8, "src")
+    with torch.cuda.device(src.device):
+        return _res(lib.validate_utf8(src.data_ptr(), src.numel(), stream_handle(stream)))
+
+
+def utf16_length_from_utf8(src: torch.Tensor, stream=None) -> Result:
+    _check(src, _U8, "src")
+    with torch.cuda.device(src.device):
+        return _res(lib.utf16_length_from_utf8(src.data_ptr(), src.numel(), stream_handle(stream)))
+
+
+def convert_utf8_to_utf16le(src: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Returns (int16 tensor holding the UTF-16LE words, Result). With `out`
+    the words go there (capacity = out.numel()) and `out` is returned whole."""
+    _check(src, _U8, "src")
+    with torch.cuda.device(src.device):
+        dst = out if out is not None else torch.empty(max(src.numel(), 1), dtype=torch.int16, device=src.device)
+        _check(dst, _U16, "out")
+        r = _res(lib.convert_utf8_to_utf16le(src.data_ptr(), src.numel(), dst.data_ptr(),
+                                             dst.numel() if out is not None else src.numel(),
+                                             stream_handle(stream)))
+    if out is not None:
+        return out, r
+    return dst[: r.count] if r.error == OK else dst[:0], r
+
+
+def validate_utf16le(src: torch.Tensor, stream=None) -> Result:
+    _check(src, _U16, "src")
+    with torch.cuda.device(src.device):
+        return _res(lib.validate_utf16le(src.data_ptr(), src.numel(), stream_handle(stream)))
+
+
+def utf8_length_from_utf16le(src: torch.Tensor, stream=None) -> Result:
+    _check(src, _U16, "src")
+    with torch.cuda.device(src.device):
+        return _res(lib.utf8_length_from_utf16le(src.data_ptr(), src.numel(), stream_handle(stream)))
+
+
+def convert_utf16le_to_utf8(src: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """Returns (uint8 tensor holding the UTF-8 bytes, Result)."""
+    _check(src, _U16, "src")
+    with torch.cuda.device(src.device):
+        dst = out if out is not None else torch.empty(max(3 * src.numel(), 1), dtype=torch.uint8, device=src.device)
+        _check(dst, _U8, "out")
+        r = _res(lib.convert_utf16le_to_utf8(src.data_ptr(), src.numel(), dst.data_ptr(),
+                                             dst.numel() if out is not None else 3 * src.numel(),
+                                             stream_handle(stream)))
+    if out is not None:
+        return out, r
+    return dst[: r.count] if r.error == OK else dst[:0], r
+
+
+def workspace(op: int, n_units: int, device=None) -> torch.Tensor:
+    """A zero-filled workspace tensor for the *_async calls (256-byte aligned)."""
+    nbytes = int(lib.hu_workspace_bytes(op, n_units))
+    return torch.zeros(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+
+
+def workspace_ptr(ws: torch.Tensor) -> tuple[int, int]:
+    """(aligned device pointer, usable bytes) of a workspace tensor."""
+    p = ws.data_ptr()
+    a = (p + 255) & ~255
+    return a, ws.numel() - (a - p)
+
+
+def result_from_device(rec: torch.Tensor) -> Result:
+    """Decode a 16-byte device result record (uint8 tensor) on the host."""
+    b = rec.cpu().numpy().tobytes()[:16]
+    r = HuResult.from_buffer_copy(b)
+    return _res(r)

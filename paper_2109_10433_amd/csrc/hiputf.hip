@@ -1,0 +1,472 @@
+// hiputf.hip - C-ABI runtime for validating UTF-8 <-> UTF-16LE transcoding
+// (declarations and contracts in include/hiputf.h).
+//
+// A call = one persistent tile kernel (u8_kernels.hpp / u16_kernels.hpp) plus
+// one single-workgroup finalize kernel that turns the workspace's error key and
+// totals into the hu_result, then resets the workspace for the next call.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "hiputf.h"
+#include "u16_kernels.hpp"
+
+namespace hu {
+
+// ------------------------------------------------------------ first error (UTF-8)
+// Kind of the sequence that starts at p (p < n), testing the six rules of
+// section 3 in reading order; on success *len is the sequence length.
+__device__ int utf8_sequence_kind(const uint8_t *s, unsigned long long n, unsigned long long p, int *len)
+{
+    const unsigned int b = s[p];
+    if (b < 0x80u) {
+        *len = 1;
+        return HU_OK;
+    }
+    if (b < 0xC0u)
+        return HU_ERR_STRAY_CONTINUATION;
+    if (b >= 0xF8u)
+        return HU_ERR_BAD_LEAD;
+    const int L = b >= 0xF0u ? 4 : (b >= 0xE0u ? 3 : 2);
+    if (p + (unsigned long long)L > n)
+        return HU_ERR_TRUNCATED;
+    unsigned int v = b & (L == 2 ? 0x1Fu : (L == 3 ? 0x0Fu : 0x07u));
+    for (int i = 1; i < L; ++i) {
+        const unsigned int c = s[p + i];
+        if ((c & 0xC0u) != 0x80u)
+            return HU_ERR_TRUNCATED;
+        v = (v << 6) | (c & 0x3Fu);
+    }
+    const unsigned int smallest = L == 2 ? 0x80u : (L == 3 ? 0x800u : 0x10000u);
+    if (v < smallest)
+        return HU_ERR_OVERLONG;
+    if (v > 0x10FFFFu)
+        return HU_ERR_TOO_LARGE;
+    if (v >= 0xD800u && v <= 0xDFFFu)
+        return HU_ERR_SURROGATE;
+    *len = L;
+    return HU_OK;
+}
+
+// Given the first flagged byte f (P <= f <= P + 3, P = end of the longest
+// valid prefix), step back to a character boundary at or before P and decode
+// forward until the first ill-formed sequence.
+__device__ hu_result resolve_utf8(const uint8_t *s, unsigned long long n, unsigned long long f)
+{
+    hu_result r;
+    r.reserved = 0;
+    unsigned long long p = f >= 3 ? f - 3 : 0;
+    for (int steps = 0; steps < 4 && p > 0 && (s[p] & 0xC0u) == 0x80u; ++steps)
+        --p;
+    while (p < n && p <= f) {
+        int len = 0;
+        const int kind = utf8_sequence_kind(s, n, p, &len);
+        if (kind != HU_OK) {
+            r.error = kind;
+            r.count = p;
+            return r;
+        }
+        p += (unsigned long long)len;
+    }
+    r.error = HU_ERR_DEVICE;   // flags and decoding disagree: never expected
+    r.count = 0;
+    return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const uint8_t *src, unsigned long long n,
+                                                     unsigned long long cap, int op, WsHeader *hdr,
+                                                     unsigned long long *status,
+                                                     unsigned long long status_cap, hu_result *out)
+{
+    __shared__ int wrap;
+    if (threadIdx.x == 0) {
+        const unsigned long long key = hdr->err_key;
+        const unsigned long long total = hdr->total;
+        hu_result r;
+        r.reserved = 0;
+        if (hdr->hang) {
+            r.error = HU_ERR_DEVICE;
+            r.count = 0;
+        } else if (key != 0) {
+            const unsigned long long f = ~key;
+            if (op <= HU_OP_CONVERT_UTF8_TO_UTF16LE) {
+                r = resolve_utf8(src, n, f);
+            } else {
+                r.error = HU_ERR_UNPAIRED_SURROGATE;
+                r.count = f;
+            }
+        } else if (op == HU_OP_VALIDATE_UTF8 || op == HU_OP_VALIDATE_UTF16LE) {
+            r.error = HU_OK;
+            r.count = n;
+        } else if ((op == HU_OP_CONVERT_UTF8_TO_UTF16LE || op == HU_OP_CONVERT_UTF16LE_TO_UTF8) &&
+                   total > cap) {
+            r.error = HU_ERR_OUTPUT_TOO_SMALL;
+            r.count = total;
+        } else {
+            r.error = HU_OK;
+            r.count = total;
+        }
+        *out = r;
+        hdr->tile_counter = 0;
+        hdr->err_key = 0;
+        hdr->total = 0;
+        hdr->hang = 0;
+        const unsigned int e = (hdr->epoch + 1u) & kEpochMask;
+        hdr->epoch = e;
+        wrap = (e == 0);
+    }
+    __syncthreads();
+    if (wrap) {
+        // status words of the era that used tag 0 would look current again
+        for (unsigned long long i = threadIdx.x; i < status_cap; i += kBlock)
+            status[i] = 0;
+    }
+}
+
+__global__ void k_fill_zero(unsigned int *p, unsigned long long n_words)
+{
+    for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n_words;
+         i += (unsigned long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ------------------------------------------------------------ launch helpers
+struct DeviceInfo {
+    int cus = 0;
+    std::map<const void *, int> blocks_per_cu;
+};
+
+std::mutex g_info_mu;
+std::map<int, DeviceInfo> g_info;
+
+int max_resident_blocks(const void *kernel)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 0;
+    std::lock_guard<std::mutex> lk(g_info_mu);
+    DeviceInfo &di = g_info[dev];
+    if (di.cus == 0) {
+        if (hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+    }
+    auto it = di.blocks_per_cu.find(kernel);
+    if (it == di.blocks_per_cu.end()) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1)
+            nb = 1;
+        it = di.blocks_per_cu.emplace(kernel, nb).first;
+    }
+    return di.cus * it->second;
+}
+
+constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 bits
+
+unsigned long long tiles_for(int op, const void *src, unsigned long long n_units)
+{
+    const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
+    const unsigned long long bytes = u16 ? 2 * n_units : n_units;
+    const unsigned long long off = (unsigned long long)((uintptr_t)src & 15u);
+    return (off + bytes + kTile - 1) / kTile;
+}
+
+int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
+            hu_result *d_result, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
+    if (op < 0 || op > HU_OP_CONVERT_UTF16LE_TO_UTF8 || d_result == nullptr || ws == nullptr ||
+        ((uintptr_t)ws & 255u) != 0 || n > kMaxUnits)
+        return HU_ERR_INVALID_ARGUMENT;
+    if (n > 0 && src == nullptr)
+        return HU_ERR_INVALID_ARGUMENT;
+    if (cap > 0 && dst == nullptr)
+        return HU_ERR_INVALID_ARGUMENT;
+    if (u16 && ((uintptr_t)src & 1u))
+        return HU_ERR_INVALID_ARGUMENT;
+    if (op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u))
+        return HU_ERR_INVALID_ARGUMENT;
+    const unsigned long long n_tiles = n ? tiles_for(op, src, n) : 0;
+    if (ws_bytes < kHeaderBytes + 8 * n_tiles)
+        return HU_ERR_INVALID_ARGUMENT;
+
+    WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
+    unsigned long long *status = reinterpret_cast<unsigned long long *>((char *)ws + kHeaderBytes);
+    const unsigned long long status_cap = (ws_bytes - kHeaderBytes) / 8;
+
+    if (n_tiles > 0) {
+        const uint8_t *base = (const uint8_t *)((uintptr_t)src & ~(uintptr_t)15);
+        const unsigned long long off_b = (unsigned long long)((uintptr_t)src & 15u);
+        const void *kfn = nullptr;
+#define HU_PICK(KERNEL) (reinterpret_cast<const void *>(&KERNEL))
+        switch (op) {
+        case HU_OP_VALIDATE_UTF8: kfn = HU_PICK(k_u8_single<kValidate>); break;
+        case HU_OP_UTF16_LENGTH_FROM_UTF8: kfn = HU_PICK(k_u8_single<kLength>); break;
+        case HU_OP_CONVERT_UTF8_TO_UTF16LE: kfn = HU_PICK(k_u8_single<kConvert>); break;
+        case HU_OP_VALIDATE_UTF16LE: kfn = HU_PICK(k_u16_single<kValidate>); break;
+        case HU_OP_UTF8_LENGTH_FROM_UTF16LE: kfn = HU_PICK(k_u16_single<kLength>); break;
+        default: kfn = HU_PICK(k_u16_single<kConvert>); break;
+        }
+#undef HU_PICK
+        const int max_blocks = max_resident_blocks(kfn);
+        if (max_blocks <= 0)
+            return HU_ERR_DEVICE;
+        const unsigned int grid = (unsigned int)(n_tiles < (unsigned long long)max_blocks ? n_tiles : max_blocks);
+        if (!u16) {
+            U8Doc d{base, off_b, n, (uint16_t *)dst, cap};
+            switch (op) {
+            case HU_OP_VALIDATE_UTF8:
+                hipLaunchKernelGGL(k_u8_single<kValidate>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
+                break;
+            case HU_OP_UTF16_LENGTH_FROM_UTF8:
+                hipLaunchKernelGGL(k_u8_single<kLength>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
+                break;
+            default:
+                hipLaunchKernelGGL(k_u8_single<kConvert>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
+                break;
+            }
+        } else {
+            U16Doc d{base, off_b / 2, n, (uint8_t *)dst, cap};
+            switch (op) {
+            case HU_OP_VALIDATE_UTF16LE:
+                hipLaunchKernelGGL(k_u16_single<kValidate>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
+                break;
+            case HU_OP_UTF8_LENGTH_FROM_UTF16LE:
+                hipLaunchKernelGGL(k_u16_single<kLength>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
+                break;
+            default:
+                hipLaunchKernelGGL(k_u16_single<kConvert>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
+                break;
+            }
+        }
+        if (hipGetLastError() != hipSuccess)
+            return HU_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, stream, (const uint8_t *)src, n, cap, op, hdr,
+                       status, status_cap, d_result);
+    if (hipGetLastError() != hipSuccess)
+        return HU_ERR_DEVICE;
+    return HU_OK;
+}
+
+// ------------------------------------------------------------ synchronous path
+struct StreamSlot {
+    std::mutex mu;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    hu_result *d_result = nullptr;
+    hu_result *h_result = nullptr;   // pinned
+};
+
+std::mutex g_slots_mu;
+std::map<std::pair<int, hipStream_t>, StreamSlot *> g_slots;
+
+StreamSlot *slot_for(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_slots_mu);
+    StreamSlot *&s = g_slots[std::make_pair(dev, stream)];
+    if (s == nullptr)
+        s = new StreamSlot();
+    return s;
+}
+
+hu_result make_result(int error, unsigned long long count)
+{
+    hu_result r;
+    r.error = error;
+    r.reserved = 0;
+    r.count = count;
+    return r;
+}
+
+hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
+                   hipStream_t stream)
+{
+    const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
+    if (n > kMaxUnits || (n > 0 && src == nullptr) || (cap > 0 && dst == nullptr) ||
+        (u16 && ((uintptr_t)src & 1u)) || (op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u)))
+        return make_result(HU_ERR_INVALID_ARGUMENT, 0);
+    if (n == 0)
+        return make_result(HU_OK, 0);
+    StreamSlot *slot = slot_for(stream);
+    if (slot == nullptr)
+        return make_result(HU_ERR_DEVICE, 0);
+    std::lock_guard<std::mutex> lk(slot->mu);
+    const size_t need = kHeaderBytes + 8 * tiles_for(op, src, n);
+    if (slot->d_result == nullptr) {
+        if (hipMalloc((void **)&slot->d_result, 256) != hipSuccess ||
+            hipHostMalloc((void **)&slot->h_result, sizeof(hu_result), hipHostMallocDefault) != hipSuccess) {
+            slot->d_result = nullptr;
+            return make_result(HU_ERR_DEVICE, 0);
+        }
+    }
+    if (slot->ws_bytes < need) {
+        // the old workspace may still be in use by work queued on this stream
+        if (slot->ws != nullptr) {
+            if (hipStreamSynchronize(stream) != hipSuccess)
+                return make_result(HU_ERR_DEVICE, 0);
+            (void)hipFree(slot->ws);
+            slot->ws = nullptr;
+            slot->ws_bytes = 0;
+        }
+        size_t bytes = need + need / 4;
+        if (hipMalloc(&slot->ws, bytes) != hipSuccess || hipMemset(slot->ws, 0, bytes) != hipSuccess) {
+            slot->ws = nullptr;
+            return make_result(HU_ERR_DEVICE, 0);
+        }
+        slot->ws_bytes = bytes;
+    }
+    const int rc = enqueue(op, src, n, dst, cap, slot->d_result, slot->ws, slot->ws_bytes, stream);
+    if (rc != HU_OK)
+        return make_result(rc, 0);
+    if (hipMemcpyAsync(slot->h_result, slot->d_result, sizeof(hu_result), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return make_result(HU_ERR_DEVICE, 0);
+    return *slot->h_result;
+}
+
+}  // namespace hu
+
+// ------------------------------------------------------------ C ABI
+using hu::run_sync;
+
+extern "C" {
+
+hu_result validate_utf8(const uint8_t *src, size_t n_bytes, void *stream)
+{
+    return run_sync(HU_OP_VALIDATE_UTF8, src, n_bytes, nullptr, 0, (hipStream_t)stream);
+}
+
+hu_result utf16_length_from_utf8(const uint8_t *src, size_t n_bytes, void *stream)
+{
+    return run_sync(HU_OP_UTF16_LENGTH_FROM_UTF8, src, n_bytes, nullptr, 0, (hipStream_t)stream);
+}
+
+hu_result convert_utf8_to_utf16le(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                  void *stream)
+{
+    return run_sync(HU_OP_CONVERT_UTF8_TO_UTF16LE, src, n_bytes, dst, dst_cap_words, (hipStream_t)stream);
+}
+
+hu_result validate_utf16le(const uint16_t *src, size_t n_words, void *stream)
+{
+    return run_sync(HU_OP_VALIDATE_UTF16LE, src, n_words, nullptr, 0, (hipStream_t)stream);
+}
+
+hu_result utf8_length_from_utf16le(const uint16_t *src, size_t n_words, void *stream)
+{
+    return run_sync(HU_OP_UTF8_LENGTH_FROM_UTF16LE, src, n_words, nullptr, 0, (hipStream_t)stream);
+}
+
+hu_result convert_utf16le_to_utf8(const uint16_t *src, size_t n_words, uint8_t *dst, size_t dst_cap_bytes,
+                                  void *stream)
+{
+    return run_sync(HU_OP_CONVERT_UTF16LE_TO_UTF8, src, n_words, dst, dst_cap_bytes, (hipStream_t)stream);
+}
+
+size_t hu_workspace_bytes(int op, size_t n_units)
+{
+    if (op < 0 || op > HU_OP_CONVERT_UTF16LE_TO_UTF8)
+        return 0;
+    // worst case over source alignments: 15 bytes of offset
+    const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
+    return hu::kHeaderBytes + 8 * ((bytes + 15 + hu::kTile - 1) / hu::kTile);
+}
+
+int hu_workspace_init(void *ws, size_t ws_bytes, void *stream)
+{
+    if (ws == nullptr || ((uintptr_t)ws & 255u) != 0 || ws_bytes < hu::kHeaderBytes)
+        return HU_ERR_INVALID_ARGUMENT;
+    const unsigned long long words = ws_bytes / 4;
+    const unsigned int grid = (unsigned int)((words + 255) / 256 < 1024 ? (words + 255) / 256 : 1024);
+    hipLaunchKernelGGL(hu::k_fill_zero, dim3(grid), dim3(256), 0, (hipStream_t)stream, (unsigned int *)ws, words);
+    return hipGetLastError() == hipSuccess ? HU_OK : HU_ERR_DEVICE;
+}
+
+int validate_utf8_async(const uint8_t *src, size_t n_bytes, hu_result *d_result, void *ws, size_t ws_bytes,
+                        void *stream)
+{
+    return hu::enqueue(HU_OP_VALIDATE_UTF8, src, n_bytes, nullptr, 0, d_result, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int utf16_length_from_utf8_async(const uint8_t *src, size_t n_bytes, hu_result *d_result, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_UTF16_LENGTH_FROM_UTF8, src, n_bytes, nullptr, 0, d_result, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+int convert_utf8_to_utf16le_async(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                  hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_CONVERT_UTF8_TO_UTF16LE, src, n_bytes, dst, dst_cap_words, d_result, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+int validate_utf16le_async(const uint16_t *src, size_t n_words, hu_result *d_result, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    return hu::enqueue(HU_OP_VALIDATE_UTF16LE, src, n_words, nullptr, 0, d_result, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+int utf8_length_from_utf16le_async(const uint16_t *src, size_t n_words, hu_result *d_result, void *ws,
+                                   size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_UTF8_LENGTH_FROM_UTF16LE, src, n_words, nullptr, 0, d_result, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst, size_t dst_cap_bytes,
+                                  hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_CONVERT_UTF16LE_TO_UTF8, src, n_words, dst, dst_cap_bytes, d_result, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+const char *hu_error_name(int error)
+{
+    switch (error) {
+    case HU_OK: return "OK";
+    case HU_ERR_BAD_LEAD: return "BAD_LEAD";
+    case HU_ERR_TRUNCATED: return "TRUNCATED";
+    case HU_ERR_STRAY_CONTINUATION: return "STRAY_CONTINUATION";
+    case HU_ERR_OVERLONG: return "OVERLONG";
+    case HU_ERR_TOO_LARGE: return "TOO_LARGE";
+    case HU_ERR_SURROGATE: return "SURROGATE";
+    case HU_ERR_UNPAIRED_SURROGATE: return "UNPAIRED_SURROGATE";
+    case HU_ERR_OUTPUT_TOO_SMALL: return "OUTPUT_TOO_SMALL";
+    case HU_ERR_INVALID_ARGUMENT: return "INVALID_ARGUMENT";
+    case HU_ERR_DEVICE: return "DEVICE";
+    default: return "UNKNOWN";
+    }
+}
+
+void hu_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(hu::g_slots_mu);
+    for (auto &kv : hu::g_slots) {
+        hu::StreamSlot *s = kv.second;
+        std::lock_guard<std::mutex> lk2(s->mu);
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        if (hipSetDevice(kv.first.first) == hipSuccess) {
+            (void)hipDeviceSynchronize();
+            if (s->ws) (void)hipFree(s->ws);
+            if (s->d_result) (void)hipFree(s->d_result);
+            if (s->h_result) (void)hipHostFree(s->h_result);
+        }
+        (void)hipSetDevice(prev);
+        s->ws = nullptr;
+        s->d_result = nullptr;
+        s->h_result = nullptr;
+        s->ws_bytes = 0;
+    }
+}
+
+}  // extern "C"

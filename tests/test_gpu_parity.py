@@ -1,0 +1,311 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI,
+element by element (all results are integers: bit-exact)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2109_10433_amd import workloads as wl
+from tests.gpu_util import DeviceBytes, DeviceOut, say
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2109_10433_amd import binding as hu
+    TILE = 4096
+
+
+def _stream():
+    return hu.stream_handle()
+
+
+def gpu_u8(op: str, data: np.ndarray, offset: int = 0, cap_words: int | None = None, out_offset: int = 0):
+    """Run one UTF-8 entry point; returns (Result, output words or None, DeviceOut)."""
+    src = DeviceBytes(data, offset)
+    n = data.size
+    if op == "validate":
+        return _r(hu.lib.validate_utf8(src.ptr, n, _stream())), None, None
+    if op == "length":
+        return _r(hu.lib.utf16_length_from_utf8(src.ptr, n, _stream())), None, None
+    cap = n if cap_words is None else cap_words
+    out = DeviceOut(2 * cap, out_offset)
+    r = _r(hu.lib.convert_utf8_to_utf16le(src.ptr, n, out.ptr, cap, _stream()))
+    h = out.host()
+    words = out.region(h).view(np.uint16) if cap else np.zeros(0, np.uint16)
+    return r, (h, words), out
+
+
+def gpu_u16(op: str, words: np.ndarray, offset: int = 0, cap_bytes: int | None = None, out_offset: int = 0):
+    src = DeviceBytes(words.astype("<u2"), offset)
+    n = words.size
+    if op == "validate":
+        return _r(hu.lib.validate_utf16le(src.ptr, n, _stream())), None, None
+    if op == "length":
+        return _r(hu.lib.utf8_length_from_utf16le(src.ptr, n, _stream())), None, None
+    cap = 3 * n if cap_bytes is None else cap_bytes
+    out = DeviceOut(cap, out_offset)
+    r = _r(hu.lib.convert_utf16le_to_utf8(src.ptr, n, out.ptr, cap, _stream()))
+    h = out.host()
+    return r, (h, out.region(h)), out
+
+
+def _r(res):
+    return (int(res.error), int(res.count))
+
+
+def check_u8_all(data: np.ndarray, offset: int = 0, out_offset: int = 0):
+    """All three UTF-8 entry points against the oracle."""
+    ov = tuple(oracle.validate_utf8(data))
+    ol = tuple(oracle.utf16_length_from_utf8(data))
+    ow, oc = oracle.convert_utf8_to_utf16le(data)
+    assert gpu_u8("validate", data, offset)[0] == ov
+    assert gpu_u8("length", data, offset)[0] == ol
+    r, (h, words), out = gpu_u8("convert", data, offset, out_offset=out_offset)
+    assert r == tuple(oc)
+    if r[0] == 0:
+        assert np.array_equal(words[:r[1]], ow)
+        out.check_guards(h, 2 * r[1])
+    else:
+        out.check_guards(h)
+    return ov
+
+
+def check_u16_all(words: np.ndarray, offset: int = 0, out_offset: int = 0):
+    ov = tuple(oracle.validate_utf16le(words))
+    ol = tuple(oracle.utf8_length_from_utf16le(words))
+    ob, oc = oracle.convert_utf16le_to_utf8(words)
+    assert gpu_u16("validate", words, offset)[0] == ov
+    assert gpu_u16("length", words, offset)[0] == ol
+    r, (h, b), out = gpu_u16("convert", words, offset, out_offset=out_offset)
+    assert r == tuple(oc)
+    if r[0] == 0:
+        assert np.array_equal(b[:r[1]], ob)
+        out.check_guards(h, r[1])
+    else:
+        out.check_guards(h)
+    return ov
+
+
+# ---------------------------------------------------------------- 1 MiB buffer
+
+@pytest.fixture(scope="module")
+def mix1m():
+    return wl.single_buffer(1 << 20)
+
+
+def test_mixed_1mib_all_functions(mix1m):
+    say("mixed 1 MiB, all six functions")
+    assert check_u8_all(mix1m.u8) == (0, mix1m.u8.size)
+    assert check_u16_all(mix1m.u16) == (0, mix1m.u16.size)
+
+
+def test_mixed_1mib_injected_errors(mix1m):
+    for kind, data, pos in wl.single_buffer_with_errors(mix1m):
+        say("mixed 1 MiB with", kind, "at", pos)
+        assert check_u8_all(data) == (getattr(oracle, kind), pos)
+
+
+# ---------------------------------------------------------------- sizes and alignment
+
+def test_small_sizes_and_offsets():
+    text = wl.make_text("mix", 4096, wl.rng_for("small"))
+    for offset in (0, 1, 7, 15):
+        say("utf8 sizes 0..300 at offset", offset)
+        for n in range(0, 301):
+            check_u8_all(text.u8[:n], offset, out_offset=2 * (offset % 3))
+    for offset in (0, 2, 14):
+        say("utf16 sizes 0..300 at offset", offset)
+        for n in range(0, 301):
+            check_u16_all(text.u16[:n], offset, out_offset=offset % 5)
+
+
+def test_power_of_two_sizes():
+    text = wl.make_text("mix", (1 << 17) + 64, wl.rng_for("pow2"))
+    for k in range(4, 18):
+        for d in (-1, 0, 1):
+            n = (1 << k) + d
+            say("utf8/utf16 size", n)
+            check_u8_all(text.u8[:n], offset=k % 16)
+            check_u16_all(text.u16[:n], offset=2 * (k % 8))
+
+
+# ---------------------------------------------------------------- errors near tile boundaries
+
+def test_errors_around_tile_boundaries():
+    text = wl.make_text("mix", 3 * TILE + 100, wl.rng_for("tiles"))
+    rng = np.random.default_rng(3)
+    starts = text.char_starts_u8
+    for offset in (0, 5):
+        for boundary in (TILE, 2 * TILE):
+            b = boundary - offset       # tile boundaries in input coordinates
+            for d in range(-6, 7):
+                for kind in wl.UTF8_ERROR_KINDS:
+                    i = int(np.searchsorted(starts, b + d))
+                    pos = int(starts[min(i, starts.size - 2)])
+                    data, p = wl.inject_utf8_error(text.u8, starts, kind, rng, position=pos)
+                    say("tile boundary", boundary, "offset", offset, "delta", d, kind, "at", p)
+                    ov = tuple(oracle.validate_utf8(data))
+                    assert gpu_u8("validate", data, offset)[0] == ov
+                    if ov[0] != 0:
+                        assert gpu_u8("length", data, offset)[0] == ov
+                    assert gpu_u8("convert", data, offset)[0] == tuple(oracle.convert_utf8_to_utf16le(data)[1])
+                # arbitrary byte overwrites, not only at character boundaries
+                for val in (0x80, 0xBF, 0xC2, 0xE4, 0xF0, 0xF4, 0xF8, 0x41):
+                    data = text.u8.copy()
+                    data[b + d] = val
+                    ov = tuple(oracle.validate_utf8(data))
+                    assert gpu_u8("validate", data, offset)[0] == ov, (boundary, d, hex(val))
+    # UTF-16: unpaired surrogates around word tile boundaries
+    w = text.u16
+    for offset in (0, 6):
+        for boundary in (TILE // 2, TILE):
+            b = boundary - offset // 2
+            for d in range(-3, 4):
+                for val in (0xD800, 0xDBFF, 0xDC00, 0xDFFF):
+                    data = w.copy()
+                    data[b + d] = val
+                    say("utf16 tile boundary", boundary, "delta", d, hex(val))
+                    check_u16_all(data, offset)
+
+
+# ---------------------------------------------------------------- random short strings
+
+def test_random_short_strings():
+    alphabet = np.array([0x00, 0x41, 0x7F, 0x80, 0x8F, 0x90, 0x9F, 0xA0, 0xBF, 0xC0, 0xC1, 0xC2, 0xDF,
+                         0xE0, 0xE1, 0xED, 0xEF, 0xF0, 0xF1, 0xF4, 0xF5, 0xF8, 0xFF], dtype=np.uint8)
+    rng = np.random.default_rng(11)
+    say("random short UTF-8 strings")
+    for i in range(1500):
+        n = int(rng.integers(1, 40))
+        data = alphabet[rng.integers(0, alphabet.size, size=n)]
+        if i % 3 == 0:   # embed in valid context
+            data = np.concatenate([np.frombuffer(b"ab\xc3\xa9", np.uint8), data, np.frombuffer(b"z", np.uint8)])
+        check_u8_all(data, offset=int(rng.integers(0, 16)))
+    w_alpha = np.array([0x41, 0x7F, 0x80, 0x7FF, 0x800, 0xD7FF, 0xD800, 0xDBFF, 0xDC00, 0xDFFF, 0xE000,
+                        0xFFFF], dtype=np.uint16)
+    say("random short UTF-16 strings")
+    for _ in range(800):
+        n = int(rng.integers(1, 20))
+        check_u16_all(w_alpha[rng.integers(0, w_alpha.size, size=n)], offset=2 * int(rng.integers(0, 8)))
+
+
+# ---------------------------------------------------------------- capacity
+
+def test_capacity_and_guards():
+    text = wl.make_text("emoji", 10_000, wl.rng_for("cap"))
+    n16 = text.u16.size
+    for cap in (n16, n16 + 7, n16 - 1, n16 // 2, 1, 0):
+        say("utf8->16 capacity", cap, "of", n16)
+        r, (h, words), out = gpu_u8("convert", text.u8, 3, cap_words=cap, out_offset=2)
+        if cap >= n16:
+            assert r == (0, n16)
+            assert np.array_equal(words[:n16], text.u16)
+            out.check_guards(h, 2 * n16)
+        else:
+            assert r == (oracle.OUTPUT_TOO_SMALL, n16)
+            out.check_guards(h)
+    n8 = text.u8.size
+    for cap in (n8, n8 + 1, n8 - 1, 100, 0):
+        say("utf16->8 capacity", cap, "of", n8)
+        r, (h, b), out = gpu_u16("convert", text.u16, 0, cap_bytes=cap, out_offset=1)
+        if cap >= n8:
+            assert r == (0, n8) and np.array_equal(b[:n8], text.u8)
+            out.check_guards(h, n8)
+        else:
+            assert r == (oracle.OUTPUT_TOO_SMALL, n8)
+            out.check_guards(h)
+
+
+def test_invalid_arguments():
+    say("invalid arguments")
+    s = hu.stream_handle()
+    assert _r(hu.lib.validate_utf8(None, 10, s)) == (hu.INVALID_ARGUMENT, 0)
+    assert _r(hu.lib.validate_utf8(None, 0, s)) == (0, 0)
+    buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    assert _r(hu.lib.validate_utf16le(buf.data_ptr() + 1, 4, s)) == (hu.INVALID_ARGUMENT, 0)
+    assert _r(hu.lib.convert_utf8_to_utf16le(buf.data_ptr(), 4, None, 4, s)) == (hu.INVALID_ARGUMENT, 0)
+    assert _r(hu.lib.convert_utf8_to_utf16le(buf.data_ptr(), 4, buf.data_ptr() + 1, 4, s)) == \
+        (hu.INVALID_ARGUMENT, 0)
+    assert _r(hu.lib.convert_utf16le_to_utf8(buf.data_ptr(), 0, None, 0, s)) == (0, 0)
+
+
+# ---------------------------------------------------------------- async entry points
+
+def test_async_workspace_reuse():
+    text = wl.make_text("cjk", 300_000, wl.rng_for("async"))
+    src = torch.from_numpy(text.u8.copy()).cuda()
+    ws = hu.workspace(hu.OP_CONVERT_UTF8_TO_UTF16LE, src.numel())
+    wp, wb = hu.workspace_ptr(ws)
+    rec = torch.zeros(16, dtype=torch.uint8, device="cuda")
+    for n in (src.numel(), 1000, 77_777, src.numel()):
+        say("async convert n =", n)
+        dst = torch.zeros(n, dtype=torch.int16, device="cuda")
+        rc = hu.lib.convert_utf8_to_utf16le_async(src.data_ptr(), n, dst.data_ptr(), n, rec.data_ptr(), wp, wb,
+                                                  hu.stream_handle())
+        assert rc == 0
+        torch.cuda.synchronize()
+        r = hu.result_from_device(rec)
+        ow, orr = oracle.convert_utf8_to_utf16le(text.u8[:n])
+        assert r == tuple(orr)
+        if r.error == 0:
+            assert np.array_equal(dst.cpu().numpy().view(np.uint16)[:r.count], ow)
+    say("async validate with too-small workspace")
+    rc = hu.lib.validate_utf8_async(src.data_ptr(), src.numel(), rec.data_ptr(), wp, 256, hu.stream_handle())
+    assert rc == hu.INVALID_ARGUMENT
+
+
+def test_repeat_determinism():
+    text = wl.make_text("mix", 3_000_000, wl.rng_for("repeat"))
+    src = torch.from_numpy(text.u8.copy()).cuda()
+    say("repeat determinism x20")
+    first = None
+    for _ in range(20):
+        words, r = hu.convert_utf8_to_utf16le(src)
+        h = words.cpu().numpy()
+        if first is None:
+            first = h
+            assert np.array_equal(h.view(np.uint16), text.u16)
+        else:
+            assert np.array_equal(h, first)
+
+
+# ---------------------------------------------------------------- full-size profiles
+
+@pytest.mark.parametrize("profile", wl.LARGE_PROFILES)
+def test_large_profile_both_directions(profile):
+    say("generating 256 MiB", profile)
+    t = wl.large_profile(profile)
+    src = torch.from_numpy(t.u8).cuda()
+    say("256 MiB", profile, "utf8 -> utf16")
+    words, r = hu.convert_utf8_to_utf16le(src)
+    assert r == (0, t.u16.size)
+    assert np.array_equal(words.cpu().numpy().view(np.uint16), t.u16)     # CPython codec output
+    assert hu.validate_utf8(src) == (0, t.u8.size)
+    assert hu.utf16_length_from_utf8(src) == (0, t.u16.size)
+    say("256 MiB", profile, "utf16 -> utf8")
+    back, r2 = hu.convert_utf16le_to_utf8(words)
+    assert r2 == (0, t.u8.size)
+    assert np.array_equal(back.cpu().numpy(), t.u8)
+    assert hu.validate_utf16le(words) == (0, t.u16.size)
+    assert hu.utf8_length_from_utf16le(words) == (0, t.u8.size)
+    # the oracle on a sample of windows, each starting at a character boundary
+    rng = np.random.default_rng(5)
+    starts = t.char_starts_u8
+    for _ in range(8):
+        i = int(rng.integers(0, starts.size - 200_000))
+        a, b = int(starts[i]), int(starts[i + 100_000])
+        ow, orr = oracle.convert_utf8_to_utf16le(t.u8[a:b])
+        w0 = int(t.char_starts_u16[i])
+        assert np.array_equal(words[w0:w0 + ow.size].cpu().numpy().view(np.uint16), ow)
+    # one error late in the buffer
+    bad = src.clone()
+    p = int(starts[starts.size - 1000])
+    bad[p] = 0xFF
+    say("256 MiB", profile, "bad lead at", p)
+    assert hu.validate_utf8(bad) == (hu.BAD_LEAD, p)
+    del src, words, back, bad
+    torch.cuda.empty_cache()

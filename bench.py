@@ -1,0 +1,263 @@
+"""Benchmark: validating UTF-8 -> UTF-16LE (and the rest of the hot path) on
+one MI355X.
+
+A step is one pass of the whole single-buffer hot path over the large-buffer
+workload: for each of four 256 MiB UTF-8 profiles (Latin, Cyrillic, CJK,
+Emoji) convert UTF-8 -> UTF-16LE, convert UTF-16LE -> UTF-8, both length
+functions and both validations, each one kernel launch of the library's async
+entry points with caller-owned workspaces (no allocation in the timed region).
+Inputs are resident in HBM before timing starts.
+
+`value` is the validating UTF-8 -> UTF-16LE throughput in GB/s of algorithmic
+bytes (input bytes read + output bytes written), aggregated over the four
+profiles, from HIP events around each launch on the launch stream.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, AMD published peak
+METRIC = "validating UTF-8→UTF-16 GB/s and % HBM peak; batched docs/s vs plain; p99"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_u8_to_u16_256mib.json")
+
+
+def kernel_source_digest() -> str:
+    """Digest of the device sources: counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2109_10433_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hpp", ".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size-mib", type=int, default=256, help="UTF-8 bytes per profile (MiB)")
+    ap.add_argument("--profiles", default="latin,cyrillic,cjk,emoji")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="comma list of ops to run (default all): u8u16,u16u8,len8,len16,val8,val16")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build is single-GPU (got --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2109_10433_amd import binding as hu
+    from paper_2109_10433_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sh = hu.stream_handle(stream)
+    profiles = [p for p in args.profiles.split(",") if p]
+    n_bytes = args.size_mib * wl.MIB
+    ops_all = ["u8u16", "u16u8", "len8", "len16", "val8", "val16"]
+    ops = [o for o in (args.only.split(",") if args.only else ops_all) if o]
+
+    # ---------------------------------------------------------------- inputs
+    data = {}
+    t_gen = time.time()
+    for p in profiles:
+        t = wl.large_profile(p, n_bytes)
+        src8 = torch.from_numpy(t.u8.copy()).to(dev)
+        src16 = torch.from_numpy(t.u16.view(np.int16).copy()).to(dev)
+        n8, n16 = int(t.u8.size), int(t.u16.size)
+        data[p] = dict(text=t, src8=src8, src16=src16, n8=n8, n16=n16,
+                       dst16=torch.empty(n8, dtype=torch.int16, device=dev),
+                       dst8=torch.empty(n8 + 64, dtype=torch.uint8, device=dev))
+        log(f"{p}: {n8} B UTF-8, {n16} words UTF-16")
+    log(f"inputs generated and uploaded in {time.time() - t_gen:.1f}s")
+
+    max8 = max(d["n8"] for d in data.values())
+    max16 = max(d["n16"] for d in data.values())
+    ws8 = hu.workspace(hu.OP_CONVERT_UTF8_TO_UTF16LE, max8, dev)
+    ws16 = hu.workspace(hu.OP_CONVERT_UTF16LE_TO_UTF8, max16, dev)
+    w8p, w8b = hu.workspace_ptr(ws8)
+    w16p, w16b = hu.workspace_ptr(ws16)
+
+    calls = []   # (op, profile, fn, algorithmic bytes, expected (error, count))
+    for p in profiles:
+        d = data[p]
+        n8, n16 = d["n8"], d["n16"]
+        spec = {
+            "u8u16": (lambda rec, d=d: hu.lib.convert_utf8_to_utf16le_async(
+                d["src8"].data_ptr(), d["n8"], d["dst16"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
+                n8 + 2 * n16, (0, n16)),
+            "u16u8": (lambda rec, d=d: hu.lib.convert_utf16le_to_utf8_async(
+                d["src16"].data_ptr(), d["n16"], d["dst8"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
+                2 * n16 + n8, (0, n8)),
+            "len8": (lambda rec, d=d: hu.lib.utf16_length_from_utf8_async(
+                d["src8"].data_ptr(), d["n8"], rec, w8p, w8b, sh), n8, (0, n16)),
+            "len16": (lambda rec, d=d: hu.lib.utf8_length_from_utf16le_async(
+                d["src16"].data_ptr(), d["n16"], rec, w16p, w16b, sh), 2 * n16, (0, n8)),
+            "val8": (lambda rec, d=d: hu.lib.validate_utf8_async(
+                d["src8"].data_ptr(), d["n8"], rec, w8p, w8b, sh), n8, (0, n8)),
+            "val16": (lambda rec, d=d: hu.lib.validate_utf16le_async(
+                d["src16"].data_ptr(), d["n16"], rec, w16p, w16b, sh), 2 * n16, (0, n16)),
+        }
+        for op in ops:
+            fn, nbytes, expect = spec[op]
+            calls.append((op, p, fn, nbytes, expect))
+
+    recs = torch.zeros((len(calls), 16), dtype=torch.uint8, device=dev)
+    rec_ptrs = [recs[i].data_ptr() for i in range(len(calls))]
+
+    def run_step(events=None):
+        for i, (op, p, fn, _, _) in enumerate(calls):
+            if events is not None:
+                events[i][0].record(stream)
+            rc = fn(rec_ptrs[i])
+            if rc != 0:
+                raise RuntimeError(f"{op} {p}: enqueue failed with {hu.error_name(rc)}")
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        run_step()
+    torch.cuda.synchronize()
+
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        run_step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    # ---------------------------------------------------------------- check results
+    host = recs.cpu().numpy()
+    for i, (op, p, _, _, expect) in enumerate(calls):
+        r = hu.HuResult.from_buffer_copy(host[i].tobytes())
+        if (r.error, r.count) != expect:
+            raise RuntimeError(f"{op} {p}: result {(r.error, r.count)} != expected {expect}")
+    for p in profiles:
+        d = data[p]
+        if "u8u16" in ops and not torch.equal(d["dst16"][:d["n16"]], d["src16"]):
+            raise RuntimeError(f"{p}: UTF-16 output differs from the reference encoding")
+        if "u16u8" in ops and not torch.equal(d["dst8"][:d["n8"]], d["src8"]):
+            raise RuntimeError(f"{p}: UTF-8 output differs from the reference encoding")
+
+    # ---------------------------------------------------------------- timings
+    per = {}
+    for i, (op, p, _, nbytes, _) in enumerate(calls):
+        ts = [ev[s][i][0].elapsed_time(ev[s][i][1]) * 1e-3 for s in range(args.steps)]
+        per[(op, p)] = dict(bytes=nbytes, mean_s=float(np.mean(ts)), min_s=float(np.min(ts)),
+                            median_s=float(np.median(ts)))
+
+    def agg(op):
+        keys = [k for k in per if k[0] == op]
+        b = sum(per[k]["bytes"] for k in keys)
+        t = sum(per[k]["mean_s"] for k in keys)
+        return b / t / 1e9 if t > 0 else 0.0
+
+    detail = {}
+    for (op, p), v in per.items():
+        detail.setdefault(op, {})[p] = {
+            "GBps": round(v["bytes"] / v["mean_s"] / 1e9, 1),
+            "GBps_best": round(v["bytes"] / v["min_s"] / 1e9, 1),
+            "us_mean": round(v["mean_s"] * 1e6, 1),
+            "pct_peak": round(100 * v["bytes"] / v["mean_s"] / 1e9 / PEAK_HBM_GBS, 1),
+        }
+    for op in ops:
+        detail[op]["aggregate_GBps"] = round(agg(op), 1)
+
+    headline_op = "u8u16" if "u8u16" in ops else ops[0]
+    value = agg(headline_op)
+    launches = [k for k in per if k[0] == headline_op]
+    avg_bytes = sum(per[k]["bytes"] for k in launches) / len(launches)
+    avg_dur = sum(per[k]["mean_s"] for k in launches) / len(launches)
+    achieved = avg_bytes / avg_dur / 1e9
+
+    # practical ceiling: device-to-device copy of 256 MiB (read + write)
+    cbuf_a = torch.empty(n_bytes, dtype=torch.uint8, device=dev)
+    cbuf_b = torch.empty(n_bytes, dtype=torch.uint8, device=dev)
+    cbuf_a.fill_(1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        cbuf_b.copy_(cbuf_a)
+    e0.record(stream)
+    for _ in range(10):
+        cbuf_b.copy_(cbuf_a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n_bytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del cbuf_a, cbuf_b
+
+    traffic = None
+    traffic_note = "no counter file"
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("kernel_sources") == kernel_source_digest() and tf.get("size_mib") == args.size_mib:
+            traffic = tf.get("hbm_bytes_per_launch")
+            traffic_note = tf.get("note", "")
+        else:
+            traffic_note = "counters taken on other kernel sources: stale"
+
+    # ---------------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cpu_bytes, cpu_t = 0, 0.0
+        for p in profiles:
+            t = data[p]["text"]
+            t1 = time.perf_counter()
+            w, r = oracle.convert_utf8_to_utf16le(t.u8)
+            cpu_t += time.perf_counter() - t1
+            assert r.error == 0 and r.count == t.u16.size
+            cpu_bytes += t.u8.size + 2 * t.u16.size
+        cpu = {"value": round(cpu_bytes / cpu_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"validating UTF-8->UTF-16LE of the same {len(profiles)} x {args.size_mib} MiB profiles, "
+                         f"one pass each, single thread ({cpu_t:.1f} s)"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"large-buffer transcoding, {args.size_mib} MiB UTF-8 per profile",
+                   "profiles": profiles, "ops_per_step": ops, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": "k_u8_single<kConvert>", "traffic_note": traffic_note},
+        "cpu_baseline": cpu,
+        "copy_ceiling_GBps": round(copy_gbs, 1),
+        "detail": detail,
+        "kernel_sources": kernel_source_digest(),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -20,15 +20,17 @@ constexpr int kTile = kBlock * kChunk;   // tile bytes
 
 // ---------------------------------------------------------------- workspace
 // A workspace is a WsHeader followed by one 64-bit status word per tile.
-// All-zero is the initial state; every finalize kernel restores it (apart from
-// the epoch, which advances) so that the next call needs no clearing.
+// All-zero is the initial state; the last workgroup of every call restores it
+// (apart from the epoch, which advances) so that the next call needs no clearing.
 struct alignas(64) WsHeader {
     unsigned long long tile_counter;   // next tile id handed out to workgroups
     unsigned long long err_key;        // ~(first flagged position); 0 = no flag
     unsigned long long total;          // sum of the tiles' output counts
     unsigned int epoch;                // tag of this call's status words
     unsigned int hang;                 // set if a bounded wait gave up
-    unsigned long long pad[4];
+    unsigned int done;                 // workgroups of this launch that have finished
+    unsigned int pad0;
+    unsigned long long pad[3];
 };
 static_assert(sizeof(WsHeader) == 64, "header size");
 constexpr size_t kHeaderBytes = 256;   // header slot (status array stays 256-byte aligned)

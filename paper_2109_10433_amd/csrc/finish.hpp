@@ -1,0 +1,144 @@
+// finish.hpp - end of a call: the last workgroup of a launch turns the
+// workspace's error key and totals into the hu_result and resets the
+// workspace for the next call (all in the same kernel launch).
+#pragma once
+
+#include "device_common.hpp"
+#include "hiputf.h"
+
+namespace hu {
+
+// Kind of the UTF-8 sequence that starts at p (p < n), testing the six rules
+// of section 3 in reading order; on success *len is the sequence length.
+__device__ inline int utf8_sequence_kind(const uint8_t *s, unsigned long long n, unsigned long long p, int *len)
+{
+    const unsigned int b = s[p];
+    if (b < 0x80u) {
+        *len = 1;
+        return HU_OK;
+    }
+    if (b < 0xC0u)
+        return HU_ERR_STRAY_CONTINUATION;
+    if (b >= 0xF8u)
+        return HU_ERR_BAD_LEAD;
+    const int L = b >= 0xF0u ? 4 : (b >= 0xE0u ? 3 : 2);
+    if (p + (unsigned long long)L > n)
+        return HU_ERR_TRUNCATED;
+    unsigned int v = b & (L == 2 ? 0x1Fu : (L == 3 ? 0x0Fu : 0x07u));
+    for (int i = 1; i < L; ++i) {
+        const unsigned int c = s[p + i];
+        if ((c & 0xC0u) != 0x80u)
+            return HU_ERR_TRUNCATED;
+        v = (v << 6) | (c & 0x3Fu);
+    }
+    const unsigned int smallest = L == 2 ? 0x80u : (L == 3 ? 0x800u : 0x10000u);
+    if (v < smallest)
+        return HU_ERR_OVERLONG;
+    if (v > 0x10FFFFu)
+        return HU_ERR_TOO_LARGE;
+    if (v >= 0xD800u && v <= 0xDFFFu)
+        return HU_ERR_SURROGATE;
+    *len = L;
+    return HU_OK;
+}
+
+// Given the first flagged byte f (P <= f <= P + 3, P = end of the longest
+// valid prefix), step back to a character boundary at or before P and decode
+// forward to the first ill-formed sequence.
+__device__ inline hu_result resolve_utf8(const uint8_t *s, unsigned long long n, unsigned long long f)
+{
+    hu_result r;
+    r.reserved = 0;
+    unsigned long long p = f >= 3 ? f - 3 : 0;
+    for (int steps = 0; steps < 4 && p > 0 && (s[p] & 0xC0u) == 0x80u; ++steps)
+        --p;
+    while (p < n && p <= f) {
+        int len = 0;
+        const int kind = utf8_sequence_kind(s, n, p, &len);
+        if (kind != HU_OK) {
+            r.error = kind;
+            r.count = p;
+            return r;
+        }
+        p += (unsigned long long)len;
+    }
+    r.error = HU_ERR_DEVICE;   // flags and decoding disagree: never expected
+    r.count = 0;
+    return r;
+}
+
+struct CallInfo {
+    const uint8_t *src;          // first input byte
+    unsigned long long n;        // input code units
+    unsigned long long cap;      // output capacity in code units
+    int op;                      // HU_OP_*
+};
+
+// Result of the call from the workspace header (thread 0 of the last workgroup).
+__device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr)
+{
+    const unsigned long long key = __hip_atomic_load(&hdr->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long total = __hip_atomic_load(&hdr->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int hang = __hip_atomic_load(&hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hu_result r;
+    r.reserved = 0;
+    if (hang) {
+        r.error = HU_ERR_DEVICE;
+        r.count = 0;
+    } else if (key != 0) {
+        const unsigned long long f = ~key;
+        if (c.op <= HU_OP_CONVERT_UTF8_TO_UTF16LE) {
+            r = resolve_utf8(c.src, c.n, f);
+        } else {
+            r.error = HU_ERR_UNPAIRED_SURROGATE;   // the first flagged word is the first error
+            r.count = f;
+        }
+    } else if (c.op == HU_OP_VALIDATE_UTF8 || c.op == HU_OP_VALIDATE_UTF16LE) {
+        r.error = HU_OK;
+        r.count = c.n;
+    } else if ((c.op == HU_OP_CONVERT_UTF8_TO_UTF16LE || c.op == HU_OP_CONVERT_UTF16LE_TO_UTF8) &&
+               total > c.cap) {
+        r.error = HU_ERR_OUTPUT_TOO_SMALL;
+        r.count = total;
+    } else {
+        r.error = HU_OK;
+        r.count = total;
+    }
+    return r;
+}
+
+// Called by every workgroup after its last tile (all threads). The workgroup
+// that arrives last writes the result and resets the workspace.
+__device__ inline void finish_launch(const CallInfo &c, WsHeader *hdr, unsigned long long *status,
+                                     unsigned long long status_cap, hu_result *out, int *s_flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // release: this workgroup's error key / totals / status atomics are
+        // complete before it counts itself done; acquire for the last one
+        const unsigned int prev = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (*s_flag == 0)
+        return;
+    if (threadIdx.x == 0) {
+        *out = call_result(c, hdr);
+        hdr->tile_counter = 0;
+        hdr->err_key = 0;
+        hdr->total = 0;
+        hdr->hang = 0;
+        hdr->done = 0;
+        const unsigned int e = (hdr->epoch + 1u) & kEpochMask;
+        hdr->epoch = e;
+        *s_flag = (e == 0) ? 2 : 1;
+    }
+    __syncthreads();
+    if (*s_flag == 2) {
+        // status words of the era that used tag 0 would look current again
+        for (unsigned long long i = threadIdx.x; i < status_cap; i += blockDim.x)
+            status[i] = 0;
+    }
+}
+
+}  // namespace hu

@@ -1,9 +1,9 @@
 // hiputf.hip - C-ABI runtime for validating UTF-8 <-> UTF-16LE transcoding
 // (declarations and contracts in include/hiputf.h).
 //
-// A call = one persistent tile kernel (u8_kernels.hpp / u16_kernels.hpp) plus
-// one single-workgroup finalize kernel that turns the workspace's error key and
-// totals into the hu_result, then resets the workspace for the next call.
+// A call = one launch of a persistent tile kernel (u8_kernels.hpp /
+// u16_kernels.hpp) whose last workgroup writes the hu_result and resets the
+// workspace for the next call (finish.hpp).
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -14,116 +14,6 @@
 #include "u16_kernels.hpp"
 
 namespace hu {
-
-// ------------------------------------------------------------ first error (UTF-8)
-// Kind of the sequence that starts at p (p < n), testing the six rules of
-// section 3 in reading order; on success *len is the sequence length.
-__device__ int utf8_sequence_kind(const uint8_t *s, unsigned long long n, unsigned long long p, int *len)
-{
-    const unsigned int b = s[p];
-    if (b < 0x80u) {
-        *len = 1;
-        return HU_OK;
-    }
-    if (b < 0xC0u)
-        return HU_ERR_STRAY_CONTINUATION;
-    if (b >= 0xF8u)
-        return HU_ERR_BAD_LEAD;
-    const int L = b >= 0xF0u ? 4 : (b >= 0xE0u ? 3 : 2);
-    if (p + (unsigned long long)L > n)
-        return HU_ERR_TRUNCATED;
-    unsigned int v = b & (L == 2 ? 0x1Fu : (L == 3 ? 0x0Fu : 0x07u));
-    for (int i = 1; i < L; ++i) {
-        const unsigned int c = s[p + i];
-        if ((c & 0xC0u) != 0x80u)
-            return HU_ERR_TRUNCATED;
-        v = (v << 6) | (c & 0x3Fu);
-    }
-    const unsigned int smallest = L == 2 ? 0x80u : (L == 3 ? 0x800u : 0x10000u);
-    if (v < smallest)
-        return HU_ERR_OVERLONG;
-    if (v > 0x10FFFFu)
-        return HU_ERR_TOO_LARGE;
-    if (v >= 0xD800u && v <= 0xDFFFu)
-        return HU_ERR_SURROGATE;
-    *len = L;
-    return HU_OK;
-}
-
-// Given the first flagged byte f (P <= f <= P + 3, P = end of the longest
-// valid prefix), step back to a character boundary at or before P and decode
-// forward until the first ill-formed sequence.
-__device__ hu_result resolve_utf8(const uint8_t *s, unsigned long long n, unsigned long long f)
-{
-    hu_result r;
-    r.reserved = 0;
-    unsigned long long p = f >= 3 ? f - 3 : 0;
-    for (int steps = 0; steps < 4 && p > 0 && (s[p] & 0xC0u) == 0x80u; ++steps)
-        --p;
-    while (p < n && p <= f) {
-        int len = 0;
-        const int kind = utf8_sequence_kind(s, n, p, &len);
-        if (kind != HU_OK) {
-            r.error = kind;
-            r.count = p;
-            return r;
-        }
-        p += (unsigned long long)len;
-    }
-    r.error = HU_ERR_DEVICE;   // flags and decoding disagree: never expected
-    r.count = 0;
-    return r;
-}
-
-__global__ __launch_bounds__(kBlock) void k_finalize(const uint8_t *src, unsigned long long n,
-                                                     unsigned long long cap, int op, WsHeader *hdr,
-                                                     unsigned long long *status,
-                                                     unsigned long long status_cap, hu_result *out)
-{
-    __shared__ int wrap;
-    if (threadIdx.x == 0) {
-        const unsigned long long key = hdr->err_key;
-        const unsigned long long total = hdr->total;
-        hu_result r;
-        r.reserved = 0;
-        if (hdr->hang) {
-            r.error = HU_ERR_DEVICE;
-            r.count = 0;
-        } else if (key != 0) {
-            const unsigned long long f = ~key;
-            if (op <= HU_OP_CONVERT_UTF8_TO_UTF16LE) {
-                r = resolve_utf8(src, n, f);
-            } else {
-                r.error = HU_ERR_UNPAIRED_SURROGATE;
-                r.count = f;
-            }
-        } else if (op == HU_OP_VALIDATE_UTF8 || op == HU_OP_VALIDATE_UTF16LE) {
-            r.error = HU_OK;
-            r.count = n;
-        } else if ((op == HU_OP_CONVERT_UTF8_TO_UTF16LE || op == HU_OP_CONVERT_UTF16LE_TO_UTF8) &&
-                   total > cap) {
-            r.error = HU_ERR_OUTPUT_TOO_SMALL;
-            r.count = total;
-        } else {
-            r.error = HU_OK;
-            r.count = total;
-        }
-        *out = r;
-        hdr->tile_counter = 0;
-        hdr->err_key = 0;
-        hdr->total = 0;
-        hdr->hang = 0;
-        const unsigned int e = (hdr->epoch + 1u) & kEpochMask;
-        hdr->epoch = e;
-        wrap = (e == 0);
-    }
-    __syncthreads();
-    if (wrap) {
-        // status words of the era that used tag 0 would look current again
-        for (unsigned long long i = threadIdx.x; i < status_cap; i += kBlock)
-            status[i] = 0;
-    }
-}
 
 __global__ void k_fill_zero(unsigned int *p, unsigned long long n_words)
 {
@@ -195,56 +85,53 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     unsigned long long *status = reinterpret_cast<unsigned long long *>((char *)ws + kHeaderBytes);
     const unsigned long long status_cap = (ws_bytes - kHeaderBytes) / 8;
 
-    if (n_tiles > 0) {
-        const uint8_t *base = (const uint8_t *)((uintptr_t)src & ~(uintptr_t)15);
-        const unsigned long long off_b = (unsigned long long)((uintptr_t)src & 15u);
-        const void *kfn = nullptr;
+    const uint8_t *base = (const uint8_t *)((uintptr_t)src & ~(uintptr_t)15);
+    const unsigned long long off_b = (unsigned long long)((uintptr_t)src & 15u);
+    const void *kfn = nullptr;
 #define HU_PICK(KERNEL) (reinterpret_cast<const void *>(&KERNEL))
-        switch (op) {
-        case HU_OP_VALIDATE_UTF8: kfn = HU_PICK(k_u8_single<kValidate>); break;
-        case HU_OP_UTF16_LENGTH_FROM_UTF8: kfn = HU_PICK(k_u8_single<kLength>); break;
-        case HU_OP_CONVERT_UTF8_TO_UTF16LE: kfn = HU_PICK(k_u8_single<kConvert>); break;
-        case HU_OP_VALIDATE_UTF16LE: kfn = HU_PICK(k_u16_single<kValidate>); break;
-        case HU_OP_UTF8_LENGTH_FROM_UTF16LE: kfn = HU_PICK(k_u16_single<kLength>); break;
-        default: kfn = HU_PICK(k_u16_single<kConvert>); break;
-        }
-#undef HU_PICK
-        const int max_blocks = max_resident_blocks(kfn);
-        if (max_blocks <= 0)
-            return HU_ERR_DEVICE;
-        const unsigned int grid = (unsigned int)(n_tiles < (unsigned long long)max_blocks ? n_tiles : max_blocks);
-        if (!u16) {
-            U8Doc d{base, off_b, n, (uint16_t *)dst, cap};
-            switch (op) {
-            case HU_OP_VALIDATE_UTF8:
-                hipLaunchKernelGGL(k_u8_single<kValidate>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
-                break;
-            case HU_OP_UTF16_LENGTH_FROM_UTF8:
-                hipLaunchKernelGGL(k_u8_single<kLength>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
-                break;
-            default:
-                hipLaunchKernelGGL(k_u8_single<kConvert>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
-                break;
-            }
-        } else {
-            U16Doc d{base, off_b / 2, n, (uint8_t *)dst, cap};
-            switch (op) {
-            case HU_OP_VALIDATE_UTF16LE:
-                hipLaunchKernelGGL(k_u16_single<kValidate>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
-                break;
-            case HU_OP_UTF8_LENGTH_FROM_UTF16LE:
-                hipLaunchKernelGGL(k_u16_single<kLength>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
-                break;
-            default:
-                hipLaunchKernelGGL(k_u16_single<kConvert>, dim3(grid), dim3(kBlock), 0, stream, d, n_tiles, hdr, status);
-                break;
-            }
-        }
-        if (hipGetLastError() != hipSuccess)
-            return HU_ERR_DEVICE;
+    switch (op) {
+    case HU_OP_VALIDATE_UTF8: kfn = HU_PICK(k_u8_single<kValidate>); break;
+    case HU_OP_UTF16_LENGTH_FROM_UTF8: kfn = HU_PICK(k_u8_single<kLength>); break;
+    case HU_OP_CONVERT_UTF8_TO_UTF16LE: kfn = HU_PICK(k_u8_single<kConvert>); break;
+    case HU_OP_VALIDATE_UTF16LE: kfn = HU_PICK(k_u16_single<kValidate>); break;
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: kfn = HU_PICK(k_u16_single<kLength>); break;
+    default: kfn = HU_PICK(k_u16_single<kConvert>); break;
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, stream, (const uint8_t *)src, n, cap, op, hdr,
-                       status, status_cap, d_result);
+#undef HU_PICK
+    const int max_blocks = max_resident_blocks(kfn);
+    if (max_blocks <= 0)
+        return HU_ERR_DEVICE;
+    // at least one workgroup: with no tiles it only writes the result
+    const unsigned int grid =
+        (unsigned int)(n_tiles == 0 ? 1ull : (n_tiles < (unsigned long long)max_blocks ? n_tiles : max_blocks));
+    const dim3 g(grid), b(kBlock);
+    if (!u16) {
+        U8Doc d{base, off_b, n, (uint16_t *)dst, cap};
+        switch (op) {
+        case HU_OP_VALIDATE_UTF8:
+            hipLaunchKernelGGL(k_u8_single<kValidate>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
+            break;
+        case HU_OP_UTF16_LENGTH_FROM_UTF8:
+            hipLaunchKernelGGL(k_u8_single<kLength>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
+            break;
+        default:
+            hipLaunchKernelGGL(k_u8_single<kConvert>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
+            break;
+        }
+    } else {
+        U16Doc d{base, off_b / 2, n, (uint8_t *)dst, cap};
+        switch (op) {
+        case HU_OP_VALIDATE_UTF16LE:
+            hipLaunchKernelGGL(k_u16_single<kValidate>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
+            break;
+        case HU_OP_UTF8_LENGTH_FROM_UTF16LE:
+            hipLaunchKernelGGL(k_u16_single<kLength>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
+            break;
+        default:
+            hipLaunchKernelGGL(k_u16_single<kConvert>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
+            break;
+        }
+    }
     if (hipGetLastError() != hipSuccess)
         return HU_ERR_DEVICE;
     return HU_OK;

@@ -42,6 +42,7 @@ struct U16Shared {
     unsigned long long tmp64[kWaves];
     unsigned long long prefix;
     unsigned long long tile;
+    int flag;
 };
 
 __device__ __forceinline__ bool is_high(unsigned int w) { return (w & 0xFC00u) == 0xD800u; }
@@ -182,7 +183,8 @@ __device__ void u16_tile(U16Shared &s, const U16Doc &d, long long tile, unsigned
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_u16_single(U16Doc d, unsigned long long n_tiles, WsHeader *hdr,
-                                                       unsigned long long *status)
+                                                       unsigned long long *status, unsigned long long status_cap,
+                                                       hu_result *out)
 {
     __shared__ U16Shared s;
     const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -196,6 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_u16_single(U16Doc d, unsigned long l
         u16_tile<MODE>(s, d, (long long)tile, status, 0, epoch, hdr, &hdr->err_key, &hdr->total);
         __syncthreads();
     }
+    const CallInfo c{d.base + 2 * d.off, d.n, d.cap,
+                     MODE == kValidate ? HU_OP_VALIDATE_UTF16LE
+                                       : (MODE == kLength ? HU_OP_UTF8_LENGTH_FROM_UTF16LE : HU_OP_CONVERT_UTF16LE_TO_UTF8)};
+    finish_launch(c, hdr, status, status_cap, out, &s.flag);
 }
 
 }  // namespace hu

@@ -27,7 +27,7 @@
 //   6. look-back for the tile's output offset, then coalesced stores.
 #pragma once
 
-#include "device_common.hpp"
+#include "finish.hpp"
 
 namespace hu {
 
@@ -154,6 +154,7 @@ struct U8Shared {
     unsigned long long tmp64[kWaves];
     unsigned long long prefix;
     unsigned long long tile;
+    int flag;
 };
 
 template <int MODE>
@@ -321,10 +322,12 @@ __device__ __forceinline__ void build_pair_table(unsigned char *table)
         table[i] = pair_entry((unsigned int)i);
 }
 
-// One document; persistent workgroups take tiles from the workspace counter.
+// One document; persistent workgroups take tiles from the workspace counter;
+// the last workgroup to finish writes the call's result.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_u8_single(U8Doc d, unsigned long long n_tiles, WsHeader *hdr,
-                                                      unsigned long long *status)
+                                                      unsigned long long *status, unsigned long long status_cap,
+                                                      hu_result *out)
 {
     __shared__ U8Shared s;
     build_pair_table(s.table);
@@ -339,6 +342,10 @@ __global__ __launch_bounds__(kBlock) void k_u8_single(U8Doc d, unsigned long lon
         u8_tile<MODE>(s, d, (long long)tile, status, 0, epoch, hdr, &hdr->err_key, &hdr->total);
         __syncthreads();
     }
+    const CallInfo c{d.base + d.off, d.n, d.cap,
+                     MODE == kValidate ? HU_OP_VALIDATE_UTF8
+                                       : (MODE == kLength ? HU_OP_UTF16_LENGTH_FROM_UTF8 : HU_OP_CONVERT_UTF8_TO_UTF16LE)};
+    finish_launch(c, hdr, status, status_cap, out, &s.flag);
 }
 
 }  // namespace hu

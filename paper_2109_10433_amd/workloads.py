@@ -85,16 +85,17 @@ def hash_key(k) -> int:
 def _draw_class(rng, cc: CharClass, n: int) -> np.ndarray:
     if cc.alphabet:
         alpha = np.asarray(cc.alphabet, dtype=np.uint32)
-        return alpha[rng.integers(0, alpha.size, size=n)]
+        return alpha[rng.integers(0, alpha.size, size=n, dtype=np.uint32)]
+    if len(cc.ranges) == 1:
+        lo, hi = cc.ranges[0]
+        return rng.integers(lo, hi + 1, size=n, dtype=np.uint32)
     sizes = np.array([hi - lo + 1 for lo, hi in cc.ranges], dtype=np.int64)
-    k = rng.integers(0, int(sizes.sum()), size=n, dtype=np.int64)
-    out = np.empty(n, dtype=np.uint32)
+    k = rng.integers(0, int(sizes.sum()), size=n, dtype=np.uint32)
+    out = k.copy()
     base = 0
-    remaining = np.ones(n, dtype=bool)
     for (lo, hi), sz in zip(cc.ranges, sizes):
-        sel = remaining & (k < base + sz)
+        sel = (k >= base) & (k < base + sz)
         out[sel] = lo + (k[sel] - base)
-        remaining &= ~sel
         base += sz
     return out
 
@@ -128,33 +129,54 @@ def encode_utf16le(cps: np.ndarray) -> np.ndarray:
     return np.frombuffer(s.encode("utf-16-le"), dtype="<u2")
 
 
-def make_text(profile: str, n_bytes: int, rng: np.random.Generator, encode16: bool = True) -> Text:
-    """Text of exactly ``n_bytes`` UTF-8 bytes: characters drawn from the profile,
-    cut at the last whole character and padded with U+0020."""
+def _make_codepoints(profile: str, n_bytes: int, rng: np.random.Generator):
     classes = PROFILES[profile]
     probs = np.array([c.prob for c in classes])
-    probs = probs / probs.sum()
+    cdf = np.cumsum(probs / probs.sum())
     lens = np.array([c.utf8_len for c in classes], dtype=np.uint8)
-    mean = float((probs * lens).sum())
+    mean = float((probs / probs.sum() * lens).sum())
     cps_parts, len_parts, total = [], [], 0
     while total < n_bytes:
         m = int((n_bytes - total) / mean * 1.01) + 16
-        cls = rng.choice(len(classes), size=m, p=probs)
+        cls = np.searchsorted(cdf, rng.random(m, dtype=np.float32), side="right").astype(np.uint8)
+        np.minimum(cls, len(classes) - 1, out=cls)
         cps = np.empty(m, dtype=np.uint32)
         for i, cc in enumerate(classes):
             sel = cls == i
-            cps[sel] = _draw_class(rng, cc, int(sel.sum()))
+            cps[sel] = _draw_class(rng, cc, int(np.count_nonzero(sel)))
+        clen = lens[cls]
         cps_parts.append(cps)
-        len_parts.append(lens[cls])
-        total += int(lens[cls].sum(dtype=np.int64))
-    cps = np.concatenate(cps_parts)
-    clen = np.concatenate(len_parts)
+        len_parts.append(clen)
+        total += int(clen.sum(dtype=np.int64))
+    cps = np.concatenate(cps_parts) if len(cps_parts) > 1 else cps_parts[0]
+    clen = np.concatenate(len_parts) if len(len_parts) > 1 else len_parts[0]
     cum = np.cumsum(clen, dtype=np.int64)
     k = int(np.searchsorted(cum, n_bytes, side="right"))
     used = int(cum[k - 1]) if k else 0
     pad = n_bytes - used
     cps = np.concatenate([cps[:k], np.full(pad, 0x20, dtype=np.uint32)])
     clen = np.concatenate([clen[:k], np.ones(pad, dtype=np.uint8)])
+    return cps, clen
+
+
+_PIECE = 16 * MIB
+
+
+def make_text(profile: str, n_bytes: int, rng: np.random.Generator, encode16: bool = True) -> Text:
+    """Text of exactly ``n_bytes`` UTF-8 bytes: characters drawn from the
+    profile. Large texts are drawn as independent 16 MiB pieces (each cut at
+    its last whole character and padded with U+0020), in parallel threads."""
+    if n_bytes <= _PIECE:
+        cps, clen = _make_codepoints(profile, n_bytes, rng)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        seeds = rng.integers(0, 2**63 - 1, size=(n_bytes + _PIECE - 1) // _PIECE)
+        sizes = [min(_PIECE, n_bytes - i * _PIECE) for i in range(seeds.size)]
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            parts = list(ex.map(lambda a: _make_codepoints(profile, a[1], np.random.Generator(np.random.PCG64(int(a[0])))),
+                                zip(seeds, sizes)))
+        cps = np.concatenate([p[0] for p in parts])
+        clen = np.concatenate([p[1] for p in parts])
     u8 = encode_utf8(cps)
     assert u8.size == n_bytes
     u16 = encode_utf16le(cps) if encode16 else np.zeros(0, dtype=np.uint16)

@@ -11,12 +11,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hiputf.h"
+
 namespace hu {
 
 constexpr int kBlock = 256;       // threads per workgroup: four wave64
 constexpr int kWaves = kBlock / 64;
-constexpr int kChunk = 16;        // bytes each thread loads per tile (one dwordx4)
-constexpr int kTile = kBlock * kChunk;   // tile bytes
+constexpr int kChunk = 16;        // bytes per thread per sub-tile (one dwordx4)
+constexpr int kSub = kBlock * kChunk;    // sub-tile bytes (one coalesced load per thread)
+constexpr int kNoFlag = 0x7FFFFFFF;
+
+enum Mode { kValidate = 0, kLength = 1, kConvert = 2 };
 
 // ---------------------------------------------------------------- workspace
 // A workspace is a WsHeader followed by one 64-bit status word per tile.
@@ -68,7 +73,12 @@ constexpr unsigned int kSpinLimit = 1u << 22;
 // Decoupled look-back, executed by one whole wave64 (all 64 lanes active).
 // Returns the sum of the values of tiles [first, tile) of the chain, where
 // `first` is the chain's first tile (its predecessors belong to nobody).
-// Lane i inspects tile (t - 1 - i) of the current window of 64 predecessors.
+// Each round reads a window of 256 predecessors in one memory round trip:
+// lane l inspects tiles hi - 4l .. hi - 4l - 3 (newest first). The window is
+// wide because with hundreds of tiles in flight the nearest inclusive prefix is
+// typically hundreds of tiles back, and each status read goes to memory.
+constexpr int kLookWidth = 4;
+
 __device__ unsigned long long lookback(unsigned long long *status, long long first, long long tile,
                                        unsigned int epoch, unsigned int *hang_flag)
 {
@@ -77,35 +87,58 @@ __device__ unsigned long long lookback(unsigned long long *status, long long fir
     long long hi = tile - 1;             // newest predecessor not yet accounted
     unsigned int spins = 0;
     while (hi >= first) {
-        long long t = hi - lane;
-        unsigned long long word = 0;
-        unsigned int flag = kFlagInclusive;  // lanes past the chain's start act as a stop of value 0
-        if (t >= first) {
-            word = peek(&status[t]);
-            flag = ((word >> kEpochShift) == epoch) ? (unsigned int)((word >> kFlagShift) & 3u) : 0u;
+        unsigned int flag[kLookWidth];
+        unsigned long long val[kLookWidth];
+#pragma unroll
+        for (int j = 0; j < kLookWidth; ++j) {
+            const long long t = hi - (kLookWidth * lane + j);
+            flag[j] = kFlagInclusive;    // before the chain's start: a stop of value 0
+            val[j] = 0;
+            if (t >= first) {
+                const unsigned long long w = peek(&status[t]);
+                flag[j] = ((w >> kEpochShift) == epoch) ? (unsigned int)((w >> kFlagShift) & 3u) : 0u;
+                val[j] = w & kValueMask;
+            }
         }
-        unsigned long long pending = __ballot(flag == 0);
-        unsigned long long stops = __ballot(flag == kFlagInclusive);
-        // lowest lane index = newest tile; everything up to the first stop is needed
-        int first_stop = stops ? __ffsll((long long)stops) - 1 : 64;
-        unsigned long long needed = first_stop >= 63 ? ~0ull : ((2ull << first_stop) - 1);
-        if (pending & needed) {
+        int lstop = kLookWidth;          // first inclusive entry of this lane
+        bool lpend = false;              // an unpublished entry before it
+#pragma unroll
+        for (int j = 0; j < kLookWidth; ++j) {
+            if (lstop == kLookWidth) {
+                if (flag[j] == 0)
+                    lpend = true;
+                else if (flag[j] == kFlagInclusive)
+                    lstop = j;
+            }
+        }
+        const unsigned long long stops = __ballot(lstop < kLookWidth);
+        const int first_lane = stops ? __ffsll((long long)stops) - 1 : 64;
+        if (__ballot(lane <= first_lane && lpend)) {
             if (++spins > kSpinLimit) {
-                if (lane == 0)
-                    atomicOr(hang_flag, 1u);
+                if (lane == 0) {
+                    // completes before the caller publishes anything
+                    const unsigned int old = atomicOr(hang_flag, 1u);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    if (old == 0x5A5A5A5Au)
+                        __builtin_amdgcn_s_sleep(1);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                }
                 return 0;
             }
-            __builtin_amdgcn_s_sleep(1);
+            if (spins > 8)
+                __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        unsigned long long v = (lane <= first_stop && t >= first) ? (word & kValueMask) : 0;
-        // wave reduction of the values up to and including the first stop
+        unsigned long long v = 0;
+#pragma unroll
+        for (int j = 0; j < kLookWidth; ++j)
+            v += (lane < first_lane || (lane == first_lane && j <= lstop)) ? val[j] : 0ull;
         for (int off = 32; off > 0; off >>= 1)
             v += __shfl_xor(v, off, 64);
         sum += v;
-        if (first_stop < 64)
+        if (first_lane < 64)
             break;
-        hi -= 64;
+        hi -= 64 * kLookWidth;
         spins = 0;
     }
     return sum;
@@ -122,29 +155,6 @@ __device__ __forceinline__ unsigned int wave_inclusive_sum(unsigned int v)
             v += u;
     }
     return v;
-}
-
-// Exclusive prefix of `v` over the workgroup and the workgroup total.
-// Uses s_tmp[kWaves]; contains barriers (all threads must call it).
-__device__ __forceinline__ unsigned int block_exclusive_sum(unsigned int v, unsigned int *s_tmp,
-                                                            unsigned int *total)
-{
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    unsigned int inc = wave_inclusive_sum(v);
-    if (lane == 63)
-        s_tmp[wave] = inc;
-    __syncthreads();
-    unsigned int before = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-        unsigned int x = s_tmp[w];
-        before += (w < wave) ? x : 0u;
-        all += x;
-    }
-    *total = all;
-    __syncthreads();
-    return before + inc - v;
 }
 
 __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v, unsigned long long *s_tmp)
@@ -166,36 +176,63 @@ __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v
     return m;
 }
 
-// ---------------------------------------------------------------- loads
-// 16-byte aligned load of the granule at virtual byte position `v` of a
-// document whose bytes are [off, off + n) relative to the 16-byte aligned base.
-// Bytes outside [off, off + n) read as zero. A granule that holds at least one
-// byte of the document lies inside the pages that hold it, so the aligned
-// access never touches an unmapped page.
-__device__ __forceinline__ uint4 load_granule(const uint8_t *base, unsigned long long v,
-                                              unsigned long long off, unsigned long long end)
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long *s_tmp)
 {
-    uint4 q = make_uint4(0, 0, 0, 0);
-    if (v < end && v + 16 > off) {
-        q = *reinterpret_cast<const uint4 *>(base + v);
-        if (v < off || v + 16 > end) {
-            unsigned int lo = v < off ? (unsigned int)(off - v) : 0u;
-            unsigned int hi = v + 16 > end ? (unsigned int)(end - v) : 16u;
-            unsigned int w[4] = {q.x, q.y, q.z, q.w};
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    if (lane == 0)
+        s_tmp[wave] = v;
+    __syncthreads();
+    unsigned long long m = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                unsigned int keep = 0;
+    for (int w = 0; w < kWaves; ++w)
+        m += s_tmp[w];
+    __syncthreads();
+    return m;
+}
+
+// ---------------------------------------------------------------- loads
+// Inputs are read in 16-byte aligned granules relative to a 16-byte aligned
+// base; a document's bytes are [off, end) relative to that base. A granule
+// that holds at least one byte of the document lies inside the pages that hold
+// it, so the aligned access never touches an unmapped page. Granules with no
+// byte of the document are not read: their load is redirected to the
+// document's first granule and the result is masked to zero afterwards.
+// Loads carry no branch, so a thread can keep many of them in flight; masking
+// happens when the data is used.
+__device__ __forceinline__ uint4 load_granule_raw(const uint8_t *base, unsigned long long v, unsigned long long off,
+                                                  unsigned long long end)
+{
+    const bool any = v < end && v + 16 > off;
+    const unsigned long long a = any ? v : (off & ~15ull);
+    return *reinterpret_cast<const uint4 *>(base + a);
+}
+
+// Zero the bytes of granule q (at position v) that are outside [off, end).
+__device__ __forceinline__ uint4 mask_granule(uint4 q, unsigned long long v, unsigned long long off,
+                                              unsigned long long end)
+{
+    const long long lo_s = (long long)off - (long long)v;
+    const long long hi_s = (long long)end - (long long)v;
+    const int lo = lo_s < 0 ? 0 : (lo_s > 16 ? 16 : (int)lo_s);
+    const int hi = hi_s < 0 ? 0 : (hi_s > 16 ? 16 : (int)hi_s);
+    unsigned int w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    unsigned int pos = 4 * k + b;
-                    keep |= (pos >= lo && pos < hi) ? (0xFFu << (8 * b)) : 0u;
-                }
-                w[k] &= keep;
-            }
-            q = make_uint4(w[0], w[1], w[2], w[3]);
-        }
+    for (int k = 0; k < 4; ++k) {
+        const int lk = lo - 4 * k < 0 ? 0 : (lo - 4 * k > 4 ? 4 : lo - 4 * k);
+        const int hk = hi - 4 * k < 0 ? 0 : (hi - 4 * k > 4 ? 4 : hi - 4 * k);
+        const unsigned long long m = ((1ull << (8 * hk)) - 1) & ~((1ull << (8 * lk)) - 1);
+        w[k] &= (unsigned int)m;
     }
-    return q;
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ uint4 load_granule(const uint8_t *base, unsigned long long v, unsigned long long off,
+                                              unsigned long long end)
+{
+    return mask_granule(load_granule_raw(base, v, off, end), v, off, end);
 }
 
 }  // namespace hu

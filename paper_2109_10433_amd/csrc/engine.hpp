@@ -1,0 +1,374 @@
+// engine.hpp - tile engine shared by both transcoding directions (gfx950).
+//
+// An input is cut into tiles of U sub-tiles of 4 KiB. A workgroup of 256
+// threads loads a whole tile with U coalesced 16-byte loads per thread (the
+// next tile's loads are issued before the current tile's work, so they are in
+// flight meanwhile) and stages it in LDS with the 16 bytes on either side, so
+// every thread sees the 4 bytes before and after its 16-byte chunk. The
+// direction policy (u8_dir.hpp / u16_dir.hpp) validates and counts each chunk.
+//
+//  - validate / length: tiles are taken grid-stride; counts and the first
+//    flagged position are reduced per workgroup and added once at exit.
+//  - convert: tiles are taken in order from the workspace counter; one scan
+//    gives every chunk its offset inside the tile, a decoupled look-back gives
+//    the tile's offset in the output (device_common.hpp), then per sub-tile the
+//    chunks decode into LDS at their offsets, shifted so that LDS and global
+//    addresses agree modulo 16, and the sub-tile's output leaves in 16-byte
+//    stores.
+#pragma once
+
+#include "finish.hpp"
+#include "u16_dir.hpp"
+#include "u8_dir.hpp"
+
+namespace hu {
+
+constexpr int kSubWords = kSub / 4;
+
+struct Doc {
+    const uint8_t *base;          // 16-byte aligned address at or below the input
+    unsigned long long off_b;     // first input byte, relative to base
+    unsigned long long end_b;     // one past the last input byte, relative to base
+    unsigned long long n;         // input code units
+    void *dst;                    // output
+    unsigned long long cap;       // output capacity in code units
+};
+
+template <int U>
+constexpr int tile_words() { return 4 + U * kSubWords + 4; }
+
+template <class Dir, int U>
+struct ScanShared {
+    alignas(16) unsigned int in[tile_words<U>()];
+    alignas(16) unsigned char table[Dir::kNeedsTable ? 4096 : 16];
+    unsigned long long red[kWaves];
+    int flag;
+};
+
+template <class Dir, int U>
+struct ConvertShared {
+    alignas(16) unsigned int in[tile_words<U>()];
+    alignas(16) typename Dir::Out out[Dir::kStageUnits];
+    alignas(16) unsigned char table[Dir::kNeedsTable ? 4096 : 16];
+    unsigned int scan[U][kWaves];
+    unsigned long long red[kWaves];
+    unsigned long long prefix;
+};
+
+// Global (L2-resident) copy of the pair table -> LDS: one 16-byte load per thread.
+__device__ __forceinline__ void build_pair_table(unsigned char *table)
+{
+    static_assert(4096 == 16 * kBlock, "one granule per thread");
+    const uint4 v = reinterpret_cast<const uint4 *>(g_pair_table.e)[threadIdx.x];
+    reinterpret_cast<uint4 *>(table)[threadIdx.x] = v;
+}
+
+// Issue all loads of tile `tile`: U chunks per thread, plus (thread 0) the
+// granules just before and just after the tile. Unmasked: see stage_tile.
+template <int U>
+__device__ __forceinline__ void load_tile(const Doc &d, unsigned long long tile, uint4 q[U], uint4 &pre, uint4 &post)
+{
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        q[u] = load_granule_raw(d.base, tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
+    if (threadIdx.x == 0) {
+        pre = load_granule_raw(d.base, tv >= 16 ? tv - 16 : 0, d.off_b, d.end_b);
+        post = load_granule_raw(d.base, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
+    }
+}
+
+// Registers -> LDS: [16 bytes before | tile | 16 bytes after], with the bytes
+// outside the document zeroed (tiles that cover the document edges only).
+template <int U>
+__device__ __forceinline__ void stage_tile(unsigned int *in, const Doc &d, unsigned long long tile, uint4 q[U],
+                                           uint4 pre, uint4 post)
+{
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    if (tv < d.off_b || tv + (unsigned long long)U * kSub > d.end_b) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = mask_granule(q[u], tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        *reinterpret_cast<uint4 *>(&in[4 + u * kSubWords + 4 * threadIdx.x]) = q[u];
+    if (threadIdx.x == 0) {
+        pre = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b) : make_uint4(0, 0, 0, 0);
+        post = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
+        *reinterpret_cast<uint4 *>(&in[0]) = pre;
+        *reinterpret_cast<uint4 *>(&in[4 + U * kSubWords]) = post;
+    }
+}
+
+// This thread's chunk of sub-tile u with the 4 bytes on each side.
+__device__ __forceinline__ void read_chunk(const unsigned int *in, int u, unsigned int x[6])
+{
+    const int b = 4 + u * kSubWords + 4 * threadIdx.x;
+    const uint4 v = *reinterpret_cast<const uint4 *>(&in[b]);
+    x[0] = in[b - 1];
+    x[1] = v.x; x[2] = v.y; x[3] = v.z; x[4] = v.w;
+    x[5] = in[b + 4];
+}
+
+// Input units of the chunk at byte position cv that lie in the input.
+template <class Dir>
+__device__ __forceinline__ void chunk_range(const Doc &d, unsigned long long cv, unsigned int &lo, unsigned int &hi)
+{
+    constexpr unsigned int per = kChunk / Dir::kInUnit;
+    const unsigned long long c = cv / Dir::kInUnit, o = d.off_b / Dir::kInUnit, e = d.end_b / Dir::kInUnit;
+    lo = c < o ? (unsigned int)min(o - c, (unsigned long long)per) : 0u;
+    hi = c + per <= e ? per : (c >= e ? 0u : (unsigned int)(e - c));
+    if (hi < lo)
+        hi = lo;
+}
+
+// Validation and counting of a staged tile. Returns the per-chunk counts in
+// c[] and lowers flag_min to the first flagged input byte position.
+template <class Dir, int U, bool COUNT>
+__device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
+                                             unsigned long long tile, unsigned int c[U], unsigned long long &flag_min)
+{
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        unsigned int x[6];
+        read_chunk(in, u, x);
+        const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
+        unsigned int lo, hi;
+        chunk_range<Dir>(d, cv, lo, hi);
+        const int end_pos = (cv < d.end_b && cv + kChunk >= d.end_b) ? (int)(d.end_b - cv) : -1;
+        int f;
+        c[u] = Dir::template analyze<COUNT>(x, lo, hi, end_pos, table, &f);
+        if (f != kNoFlag) {
+            const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
+            flag_min = pos < flag_min ? pos : flag_min;
+        }
+        // keep sub-tiles from being interleaved by the scheduler (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Exclusive offsets of every thread's count for each of U sub-tiles, and the
+// sub-tile totals, with one barrier. Counts are at most 32 per thread, so two
+// sub-tiles share one 32-bit scan (a wave's total stays below 2^16).
+template <int U>
+__device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsigned int excl[U], unsigned int tot[U],
+                                                 unsigned int (*s_scan)[kWaves])
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < U; i += 2) {
+        const unsigned int v = c[i] | (c[i + 1] << 16);
+        const unsigned int inc = wave_inclusive_sum(v);
+        if (lane == 63) {
+            s_scan[i][wave] = inc & 0xFFFFu;
+            s_scan[i + 1][wave] = inc >> 16;
+        }
+        const unsigned int e = inc - v;
+        excl[i] = e & 0xFFFFu;
+        excl[i + 1] = e >> 16;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        unsigned int before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const unsigned int x = s_scan[u][w];
+            before += (w < wave) ? x : 0u;
+            all += x;
+        }
+        excl[u] += before;
+        tot[u] = __builtin_amdgcn_readfirstlane(all);   // uniform: keep it in a scalar register
+    }
+}
+
+// Copy staged output units out[0, shift + w) (valid from index `shift`) to
+// global units [gbase + shift, gbase + shift + w), where unit gbase sits at a
+// 16-byte aligned address; nothing at or past `cap` is written.
+template <class Dir>
+__device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned int shift, unsigned int w,
+                                         typename Dir::Out *dst, long long gbase, unsigned long long cap)
+{
+    using Out = typename Dir::Out;
+    constexpr unsigned int G = 16 / sizeof(Out);
+    unsigned int span = shift + w;
+    if (span > Dir::kStageUnits)
+        span = Dir::kStageUnits;   // only on invalid input
+    const unsigned int groups = (span + G - 1) / G;
+    for (unsigned int g = threadIdx.x; g < groups; g += kBlock) {
+        const unsigned int i0 = g * G;
+        const long long j0 = gbase + (long long)i0;
+        if (i0 >= shift && i0 + G <= span && j0 >= 0 && (unsigned long long)j0 + G <= cap) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(out + i0);
+            *reinterpret_cast<uint4 *>(dst + j0) = v;
+        } else {
+#pragma unroll
+            for (unsigned int k = 0; k < G; ++k) {
+                const unsigned int i = i0 + k;
+                const long long j = j0 + (long long)k;
+                if (i >= shift && i < span && j >= 0 && (unsigned long long)j < cap)
+                    dst[j] = out[i];
+            }
+        }
+    }
+}
+
+// Per-workgroup results at exit: the sum of counts (if any) and the first
+// flag, one atomic each, then the end-of-launch protocol.
+__device__ __forceinline__ void workgroup_exit(unsigned long long my_total, unsigned long long my_flag,
+                                               unsigned long long *red, const CallInfo &c, WsHeader *hdr,
+                                               unsigned long long *status, unsigned long long status_cap,
+                                               hu_result *out, int *s_flag, bool add_total)
+{
+    const unsigned long long f = block_min_u64(my_flag, red);
+    const unsigned long long t = add_total ? block_sum_u64(my_total, red) : 0ull;
+    if (threadIdx.x == 0) {
+        if (f != ~0ull)
+            atomicMax(&hdr->err_key, ~f);
+        if (add_total && t != 0)
+            atomicAdd(&hdr->total, t);
+    }
+    finish_launch(c, hdr, status, status_cap, out, s_flag, &red[0]);
+}
+
+// ------------------------------------------------------------ validate / length
+template <class Dir, int MODE, int U>
+__global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_tiles, WsHeader *hdr,
+                                                 unsigned long long *status, unsigned long long status_cap,
+                                                 hu_result *out)
+{
+    __shared__ ScanShared<Dir, U> s;
+    if (Dir::kNeedsTable)
+        build_pair_table(s.table);
+    unsigned long long my_total = 0, my_flag = ~0ull;
+    unsigned long long tile = blockIdx.x;
+    uint4 q[U], pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
+    if (tile < n_tiles)
+        load_tile<U>(d, tile, q, pre, post);
+    while (tile < n_tiles) {
+        stage_tile<U>(s.in, d, tile, q, pre, post);
+        __syncthreads();
+        const unsigned long long next = tile + gridDim.x;
+        if (next < n_tiles)
+            load_tile<U>(d, next, q, pre, post);      // in flight during this tile's work
+        unsigned int c[U];
+        analyze_tile<Dir, U, MODE == kLength>(s.in, s.table, d, tile, c, my_flag);
+        if (MODE == kLength) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                my_total += c[u];
+        }
+        __syncthreads();
+        tile = next;
+    }
+    const CallInfo c{d.base + d.off_b, d.n, d.cap, MODE == kLength ? Dir::kOpLength : Dir::kOpValidate};
+    workgroup_exit(my_total, my_flag, s.red, c, hdr, status, status_cap, out, &s.flag, MODE == kLength);
+}
+
+// ------------------------------------------------------------ convert
+// One workgroup per tile, tile = blockIdx.x. A tile only waits (in the
+// look-back) for tiles with smaller ids; workgroups are dispatched in id order
+// on each XCD, so the lowest unfinished tile always has a running workgroup and
+// all its predecessors done. No tile counter, no per-workgroup atomics: the
+// output total is the last tile's inclusive prefix, and the workgroup of the
+// last tile writes the call's result once its look-back is complete (every
+// tile publishes its status only after its error report has landed, so by
+// then all reports are in).
+template <class Dir, int U>
+__device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, WsHeader *hdr,
+                                             unsigned long long *status, unsigned long long status_cap, hu_result *out)
+{
+    using Out = typename Dir::Out;
+    __shared__ ConvertShared<Dir, U> s;
+    const int tid = threadIdx.x;
+    const unsigned long long tile = blockIdx.x;
+    const CallInfo call{d.base + d.off_b, d.n, d.cap, Dir::kOpConvert};
+    if (n_tiles == 0) {
+        if (tid == 0)
+            finish_call(call, hdr, 0ull, status, status_cap, out, &s.red[0]);
+        __syncthreads();
+        wrap_clear(status, status_cap, &s.red[0]);
+        return;
+    }
+    uint4 q[U], pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
+    load_tile<U>(d, tile, q, pre, post);
+    if (Dir::kNeedsTable)
+        build_pair_table(s.table);
+    const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    stage_tile<U>(s.in, d, tile, q, pre, post);
+    __syncthreads();
+
+    unsigned long long my_flag = ~0ull;
+    unsigned int c[U];
+    analyze_tile<Dir, U, true>(s.in, s.table, d, tile, c, my_flag);
+    const unsigned long long tile_flag = block_min_u64(my_flag, s.red);
+    unsigned int excl[U], tot[U];
+    block_scan_multi<U>(c, excl, tot, s.scan);
+    unsigned int agg = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        agg += tot[u];
+    if (tid == 0) {
+        if (tile_flag != ~0ull)
+            report_flag(hdr, tile_flag);
+        publish(&status[tile], pack_status(epoch, tile == 0 ? kFlagInclusive : kFlagAggregate, agg));
+    }
+    if (tid < 64) {
+        unsigned long long excl_tile = 0;
+        if (tile != 0)
+            excl_tile = lookback(status, 0, (long long)tile, epoch, &hdr->hang);
+        if (tid == 0) {
+            if (tile != 0)
+                publish(&status[tile], pack_status(epoch, kFlagInclusive, excl_tile + agg));
+            s.prefix = excl_tile;
+        }
+    }
+    __syncthreads();
+    unsigned long long pos = s.prefix;   // output units before this sub-tile
+    if (tile == n_tiles - 1 && tid == 0)
+        finish_call(call, hdr, pos + agg, status, status_cap, out, &s.red[0]);
+
+    Out *dst = reinterpret_cast<Out *>(d.dst);
+    // output units between dst and the 16-byte aligned address below it
+    const unsigned int dst_mis = (unsigned int)(((uintptr_t)d.dst & 15u) / sizeof(Out));
+    constexpr unsigned int G = 16 / sizeof(Out);
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
+        unsigned int x[6];
+        read_chunk(s.in, u, x);
+        unsigned int lo, hi;
+        chunk_range<Dir>(d, tv + (unsigned long long)u * kSub + (unsigned long long)tid * kChunk, lo, hi);
+        Dir::emit(x, lo, hi, s.out, shift + excl[u], Dir::kStageUnits);
+        __syncthreads();
+        copy_out<Dir>(s.out, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
+        __syncthreads();
+        pos += tot[u];
+    }
+    if (tile == n_tiles - 1)
+        wrap_clear(status, status_cap, &s.red[0]);
+}
+
+// The UTF-8 input side fits 128 registers (four waves per SIMD); the UTF-16
+// side needs more and runs at two.
+template <int U>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_convert_u8(
+    Doc d, unsigned long long n_tiles, WsHeader *hdr, unsigned long long *status, unsigned long long status_cap,
+    hu_result *out)
+{
+    convert_body<U8Dir, U>(d, n_tiles, hdr, status, status_cap, out);
+}
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_convert_u16(Doc d, unsigned long long n_tiles, WsHeader *hdr,
+                                                        unsigned long long *status, unsigned long long status_cap,
+                                                        hu_result *out)
+{
+    convert_body<U16Dir, U>(d, n_tiles, hdr, status, status_cap, out);
+}
+
+}  // namespace hu

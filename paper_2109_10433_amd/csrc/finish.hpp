@@ -74,11 +74,10 @@ struct CallInfo {
     int op;                      // HU_OP_*
 };
 
-// Result of the call from the workspace header (thread 0 of the last workgroup).
-__device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr)
+// Result of the call from the workspace header and the output total.
+__device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr, unsigned long long total)
 {
     const unsigned long long key = __hip_atomic_load(&hdr->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long total = __hip_atomic_load(&hdr->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned int hang = __hip_atomic_load(&hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     hu_result r;
     r.reserved = 0;
@@ -107,15 +106,58 @@ __device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr)
     return r;
 }
 
-// Called by every workgroup after its last tile (all threads). The workgroup
-// that arrives last writes the result and resets the workspace.
+// Report a flagged position (smallest wins) and wait until the report has
+// landed, so that a status word published afterwards implies it.
+__device__ inline void report_flag(WsHeader *hdr, unsigned long long pos)
+{
+    const unsigned long long old = atomicMax(&hdr->err_key, ~pos);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (old == 0x5A5A5A5A5A5A5A5Aull)   // consumes the returned value (forces the wait)
+        __builtin_amdgcn_s_sleep(1);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Thread 0 of the finishing workgroup: write the result, reset the header for
+// the next call (the epoch advances). Sets *s_wrap when the epoch wrapped.
+__device__ inline void finish_call(const CallInfo &c, WsHeader *hdr, unsigned long long total,
+                                   unsigned long long *status, unsigned long long status_cap, hu_result *out,
+                                   unsigned long long *s_wrap)
+{
+    *out = call_result(c, hdr, total);
+    hdr->tile_counter = 0;
+    hdr->err_key = 0;
+    hdr->total = 0;
+    hdr->hang = 0;
+    hdr->done = 0;
+    const unsigned int e = (hdr->epoch + 1u) & kEpochMask;
+    hdr->epoch = e;
+    *s_wrap = (e == 0) ? 1ull : 0ull;
+}
+
+// All threads of the finishing workgroup, after finish_call and a barrier:
+// when the epoch wrapped to 0, clear the status words so that none from the
+// previous era of tag 0 can look current.
+__device__ inline void wrap_clear(unsigned long long *status, unsigned long long status_cap,
+                                  const unsigned long long *s_wrap)
+{
+    __syncthreads();
+    if (*s_wrap) {
+        for (unsigned long long i = threadIdx.x; i < status_cap; i += blockDim.x)
+            status[i] = 0;
+    }
+}
+
+// Persistent kernels: called by every workgroup after its last tile (all
+// threads). The workgroup that arrives last writes the result and resets the
+// workspace.
 __device__ inline void finish_launch(const CallInfo &c, WsHeader *hdr, unsigned long long *status,
-                                     unsigned long long status_cap, hu_result *out, int *s_flag)
+                                     unsigned long long status_cap, hu_result *out, int *s_flag,
+                                     unsigned long long *s_wrap)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        // release: this workgroup's error key / totals / status atomics are
-        // complete before it counts itself done; acquire for the last one
+        // release: this workgroup's error key / totals are complete before it
+        // counts itself done; acquire for the last one
         const unsigned int prev = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
     }
@@ -123,22 +165,10 @@ __device__ inline void finish_launch(const CallInfo &c, WsHeader *hdr, unsigned 
     if (*s_flag == 0)
         return;
     if (threadIdx.x == 0) {
-        *out = call_result(c, hdr);
-        hdr->tile_counter = 0;
-        hdr->err_key = 0;
-        hdr->total = 0;
-        hdr->hang = 0;
-        hdr->done = 0;
-        const unsigned int e = (hdr->epoch + 1u) & kEpochMask;
-        hdr->epoch = e;
-        *s_flag = (e == 0) ? 2 : 1;
+        const unsigned long long total = __hip_atomic_load(&hdr->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        finish_call(c, hdr, total, status, status_cap, out, s_wrap);
     }
-    __syncthreads();
-    if (*s_flag == 2) {
-        // status words of the era that used tag 0 would look current again
-        for (unsigned long long i = threadIdx.x; i < status_cap; i += blockDim.x)
-            status[i] = 0;
-    }
+    wrap_clear(status, status_cap, s_wrap);
 }
 
 }  // namespace hu

@@ -1,9 +1,8 @@
 // hiputf.hip - C-ABI runtime for validating UTF-8 <-> UTF-16LE transcoding
 // (declarations and contracts in include/hiputf.h).
 //
-// A call = one launch of a persistent tile kernel (u8_kernels.hpp /
-// u16_kernels.hpp) whose last workgroup writes the hu_result and resets the
-// workspace for the next call (finish.hpp).
+// A call = one launch of a tile kernel (engine.hpp) whose last workgroup writes
+// the hu_result and resets the workspace for the next call (finish.hpp).
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -11,7 +10,7 @@
 #include <utility>
 
 #include "hiputf.h"
-#include "u16_kernels.hpp"
+#include "engine.hpp"
 
 namespace hu {
 
@@ -54,12 +53,37 @@ int max_resident_blocks(const void *kernel)
 
 constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 bits
 
+// sub-tiles per tile (tile = U x 4 KiB of input)
+constexpr int kUConvert = 4;
+constexpr int kUScan = 8;
+
+struct KernelChoice {
+    const void *fn;
+    unsigned long long tile_bytes;
+    bool one_group_per_tile;   // else: persistent, grid-stride over tiles
+};
+
+KernelChoice choose_kernel(int op)
+{
+#define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
+    switch (op) {
+    case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
+    case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
+    case HU_OP_CONVERT_UTF8_TO_UTF16LE: return {HU_K(k_convert_u8<kUConvert>), (unsigned long long)kUConvert * kSub, true};
+    case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
+    default: return {HU_K(k_convert_u16<kUConvert>), (unsigned long long)kUConvert * kSub, true};
+    }
+#undef HU_K
+}
+
 unsigned long long tiles_for(int op, const void *src, unsigned long long n_units)
 {
     const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
     const unsigned long long bytes = u16 ? 2 * n_units : n_units;
     const unsigned long long off = (unsigned long long)((uintptr_t)src & 15u);
-    return (off + bytes + kTile - 1) / kTile;
+    const unsigned long long tb = choose_kernel(op).tile_bytes;
+    return (off + bytes + tb - 1) / tb;
 }
 
 int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
@@ -83,56 +107,27 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
 
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
     unsigned long long *status = reinterpret_cast<unsigned long long *>((char *)ws + kHeaderBytes);
-    const unsigned long long status_cap = (ws_bytes - kHeaderBytes) / 8;
+    unsigned long long status_cap = (ws_bytes - kHeaderBytes) / 8;
 
+    const KernelChoice kc = choose_kernel(op);
+    unsigned long long grid_ll = 1;   // at least one workgroup: with no tiles it only writes the result
+    if (kc.one_group_per_tile) {
+        if (n_tiles > 0x7FFFFFFFull)
+            return HU_ERR_INVALID_ARGUMENT;
+        grid_ll = n_tiles ? n_tiles : 1;
+    } else {
+        const int max_blocks = max_resident_blocks(kc.fn);
+        if (max_blocks <= 0)
+            return HU_ERR_DEVICE;
+        grid_ll = n_tiles == 0 ? 1ull : (n_tiles < (unsigned long long)max_blocks ? n_tiles : max_blocks);
+    }
+    const unsigned int grid = (unsigned int)grid_ll;
     const uint8_t *base = (const uint8_t *)((uintptr_t)src & ~(uintptr_t)15);
     const unsigned long long off_b = (unsigned long long)((uintptr_t)src & 15u);
-    const void *kfn = nullptr;
-#define HU_PICK(KERNEL) (reinterpret_cast<const void *>(&KERNEL))
-    switch (op) {
-    case HU_OP_VALIDATE_UTF8: kfn = HU_PICK(k_u8_single<kValidate>); break;
-    case HU_OP_UTF16_LENGTH_FROM_UTF8: kfn = HU_PICK(k_u8_single<kLength>); break;
-    case HU_OP_CONVERT_UTF8_TO_UTF16LE: kfn = HU_PICK(k_u8_single<kConvert>); break;
-    case HU_OP_VALIDATE_UTF16LE: kfn = HU_PICK(k_u16_single<kValidate>); break;
-    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: kfn = HU_PICK(k_u16_single<kLength>); break;
-    default: kfn = HU_PICK(k_u16_single<kConvert>); break;
-    }
-#undef HU_PICK
-    const int max_blocks = max_resident_blocks(kfn);
-    if (max_blocks <= 0)
-        return HU_ERR_DEVICE;
-    // at least one workgroup: with no tiles it only writes the result
-    const unsigned int grid =
-        (unsigned int)(n_tiles == 0 ? 1ull : (n_tiles < (unsigned long long)max_blocks ? n_tiles : max_blocks));
-    const dim3 g(grid), b(kBlock);
-    if (!u16) {
-        U8Doc d{base, off_b, n, (uint16_t *)dst, cap};
-        switch (op) {
-        case HU_OP_VALIDATE_UTF8:
-            hipLaunchKernelGGL(k_u8_single<kValidate>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
-            break;
-        case HU_OP_UTF16_LENGTH_FROM_UTF8:
-            hipLaunchKernelGGL(k_u8_single<kLength>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
-            break;
-        default:
-            hipLaunchKernelGGL(k_u8_single<kConvert>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
-            break;
-        }
-    } else {
-        U16Doc d{base, off_b / 2, n, (uint8_t *)dst, cap};
-        switch (op) {
-        case HU_OP_VALIDATE_UTF16LE:
-            hipLaunchKernelGGL(k_u16_single<kValidate>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
-            break;
-        case HU_OP_UTF8_LENGTH_FROM_UTF16LE:
-            hipLaunchKernelGGL(k_u16_single<kLength>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
-            break;
-        default:
-            hipLaunchKernelGGL(k_u16_single<kConvert>, g, b, 0, stream, d, n_tiles, hdr, status, status_cap, d_result);
-            break;
-        }
-    }
-    if (hipGetLastError() != hipSuccess)
+    Doc doc{base, off_b, off_b + (u16 ? 2 * n : n), n, dst, cap};
+    unsigned long long n_tiles_arg = n_tiles;
+    void *args[] = {&doc, &n_tiles_arg, &hdr, &status, &status_cap, &d_result};
+    if (hipLaunchKernel(kc.fn, dim3(grid), dim3(kBlock), args, 0, stream) != hipSuccess)
         return HU_ERR_DEVICE;
     return HU_OK;
 }
@@ -262,7 +257,8 @@ size_t hu_workspace_bytes(int op, size_t n_units)
         return 0;
     // worst case over source alignments: 15 bytes of offset
     const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
-    return hu::kHeaderBytes + 8 * ((bytes + 15 + hu::kTile - 1) / hu::kTile);
+    const unsigned long long tb = hu::choose_kernel(op).tile_bytes;
+    return hu::kHeaderBytes + 8 * ((bytes + 15 + tb - 1) / tb);
 }
 
 int hu_workspace_init(void *ws, size_t ws_bytes, void *stream)

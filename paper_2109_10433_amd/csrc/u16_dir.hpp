@@ -1,0 +1,106 @@
+// u16_dir.hpp - UTF-16LE input side of the tile engine: validation, counting
+// and encoding of one 16-byte chunk (8 words) per thread (gfx950).
+//
+// Method (Lemire & Mula, section 5, Algorithm "UTF-16 to UTF-8"): words below
+// U+0080 give one byte, below U+0800 two, other words outside D800..DFFF three,
+// a surrogate pair four; the value's bits are split into 3/4/5 lead-byte
+// payload bits and 6-bit continuation payloads with the prefixes 11110 / 1110
+// / 110 / 10. Validation (section 3): a word in D800..DBFF must be followed by
+// one in DC00..DFFF and a word in DC00..DFFF must follow one in D800..DBFF.
+// The paper sends blocks with surrogates to a scalar path (vectorising them is
+// its stated future work, section 7); here each lane composes its pairs in
+// registers: the high word emits all four bytes and the low word none. The
+// first flagged word is exactly the first error.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace hu {
+
+__device__ __forceinline__ bool is_high(unsigned int w) { return (w & 0xFC00u) == 0xD800u; }
+__device__ __forceinline__ bool is_low(unsigned int w) { return (w & 0xFC00u) == 0xDC00u; }
+
+// UTF-8 length of the character that starts at word w: 0 for the low half of
+// a pair (its high half emits the four bytes).
+__device__ __forceinline__ unsigned int utf8_bytes_of(unsigned int w)
+{
+    return w < 0x80u ? 1u : w < 0x800u ? 2u : is_high(w) ? 4u : is_low(w) ? 0u : 3u;
+}
+
+struct U16Dir {
+    using Out = unsigned char;
+    static constexpr int kInUnit = 2;
+    static constexpr int kOutUnit = 1;
+    static constexpr bool kNeedsTable = false;
+    static constexpr int kOpValidate = HU_OP_VALIDATE_UTF16LE;
+    static constexpr int kOpLength = HU_OP_UTF8_LENGTH_FROM_UTF16LE;
+    static constexpr int kOpConvert = HU_OP_CONVERT_UTF16LE_TO_UTF8;
+    // staging bound per 4 KiB sub-tile (2048 words): valid input gives at most
+    // three bytes per word plus one (a high surrogate in the last word)
+    static constexpr unsigned int kStageUnits = 3 * (kSub / 2) + 48;
+
+    // word i (-2..9) of x[0..5]
+    __device__ __forceinline__ static unsigned int word(const unsigned int x[6], int i)
+    {
+        const int h = i + 2;
+        return (x[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
+    }
+
+    // [lo, hi): word positions of the chunk inside the input. Positions in
+    // the flag are in words relative to the chunk start.
+    template <bool COUNT>
+    __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], unsigned int lo, unsigned int hi,
+                                                           int /*end_pos*/, const unsigned char * /*table*/, int *flag)
+    {
+        unsigned int count = 0;
+        int f = kNoFlag;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const unsigned int w = word(x, j), pw = word(x, j - 1), nw = word(x, j + 1);
+            const bool in = (unsigned int)j >= lo && (unsigned int)j < hi;
+            const bool bad = (is_high(w) && !is_low(nw)) || (is_low(w) && !is_high(pw));
+            if (in && bad && f == kNoFlag)
+                f = j;
+            if (COUNT)
+                count += in ? utf8_bytes_of(w) : 0u;
+        }
+        *flag = f;
+        return count;
+    }
+
+    __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
+                                                unsigned int o, unsigned int limit)
+    {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const unsigned int w = word(x, j), nw = word(x, j + 1);
+            const unsigned int m = ((unsigned int)j >= lo && (unsigned int)j < hi) ? utf8_bytes_of(w) : 0u;
+            unsigned int b0, b1 = 0, b2 = 0, b3 = 0;
+            if (m == 4) {
+                const unsigned int cp = 0x10000u + (((w & 0x3FFu) << 10) | (nw & 0x3FFu));
+                b0 = 0xF0u | (cp >> 18);
+                b1 = 0x80u | ((cp >> 12) & 0x3Fu);
+                b2 = 0x80u | ((cp >> 6) & 0x3Fu);
+                b3 = 0x80u | (cp & 0x3Fu);
+            } else if (m == 3) {
+                b0 = 0xE0u | (w >> 12);
+                b1 = 0x80u | ((w >> 6) & 0x3Fu);
+                b2 = 0x80u | (w & 0x3Fu);
+            } else if (m == 2) {
+                b0 = 0xC0u | (w >> 6);
+                b1 = 0x80u | (w & 0x3Fu);
+            } else {
+                b0 = w;
+            }
+            if (m != 0 && o + 3 < limit) {
+                out[o] = (Out)b0;
+                if (m > 1) out[o + 1] = (Out)b1;
+                if (m > 2) out[o + 2] = (Out)b2;
+                if (m > 3) out[o + 3] = (Out)b3;
+            }
+            o += m;
+        }
+    }
+};
+
+}  // namespace hu

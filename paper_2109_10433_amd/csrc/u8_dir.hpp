@@ -1,0 +1,240 @@
+// u8_dir.hpp - UTF-8 input side of the tile engine: validation, counting and
+// decoding of one 16-byte chunk per thread (gfx950).
+//
+// Method (Lemire & Mula): section 4 transcodes UTF-8 to UTF-16 by finding
+// character starts as the bytes that are not continuation bytes (Algorithm
+// "non-validating transcoder"), with an ASCII fast path, and validates with
+// the Keiser-Lemire nibble tables (the rules are the six of section 3).
+//
+// Validation of every byte: the class bits of (previous byte high nibble,
+// previous byte low nibble, current byte high nibble) from three 16-entry
+// nibble tables, AND-ed; the tables are staged in LDS as their 4096-entry
+// product so that one LDS lookup per byte replaces three lookups and two ANDs.
+// Two continuation bytes in a row are legal exactly where the byte two back is
+// E0..FF or the byte three back is F0..FF. A lead byte among the last three
+// input bytes that needs more bytes than remain is a truncation.
+// The first flagged byte f satisfies P <= f <= P + 3, P = end of the longest
+// valid prefix (flags look only backwards, and every ill-formed sequence is
+// flagged at its first byte, its second byte or at the first byte within
+// three that should have continued it); finish.hpp decodes from just before f
+// to recover P and the rule it breaks.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace hu {
+
+// ------------------------------------------------------------ nibble tables
+// Classes of adjacent byte pairs (p, c) that break a rule of section 3. Each
+// class is a product of three nibble sets: p >> 4, p & 15 and c >> 4.
+struct PairClass {
+    unsigned short bit;
+    unsigned short prev_hi, prev_lo, cur_hi;   // sets of nibble values (bit v = value v)
+};
+
+constexpr unsigned short kAnyNibble = 0xFFFF;
+constexpr unsigned short kContNibbles = 0x0F00;      // 8..B: continuation byte
+constexpr unsigned short kAsciiNibbles = 0x00FF;     // 0..7
+constexpr unsigned short kLeadNibbles = 0xF000;      // C..F
+constexpr unsigned short kTwoConts = 1u << 8;
+
+constexpr PairClass kPairClasses[] = {
+    {1u << 0, kAsciiNibbles, kAnyNibble, kContNibbles},           // ASCII then continuation (rule 3)
+    {1u << 1, kLeadNibbles, kAnyNibble, (unsigned short)~kContNibbles},  // lead then non-continuation (rule 2)
+    {1u << 2, 1u << 0xC, 0x0003, kContNibbles},                   // C0, C1: overlong 2-byte (rule 4)
+    {1u << 3, 1u << 0xE, 1u << 0x0, 0x0300},                      // E0 80..9F: overlong 3-byte (rule 4)
+    {1u << 4, 1u << 0xE, 1u << 0xD, 0x0C00},                      // ED A0..BF: surrogate (rule 6)
+    {1u << 5, 1u << 0xF, 1u << 0x0, 0x0100},                      // F0 80..8F: overlong 4-byte (rule 4)
+    {1u << 6, 1u << 0xF, 1u << 0x4, 0x0E00},                      // F4 90..BF: above U+10FFFF (rule 5)
+    {1u << 7, 1u << 0xF, 0xFFE0, kContNibbles},                   // F5..FF then continuation (rules 1, 5)
+    {kTwoConts, kContNibbles, kAnyNibble, kContNibbles},          // two continuations: legal only as 3rd/4th byte
+};
+
+struct NibbleTables {
+    unsigned short prev_hi[16], prev_lo[16], cur_hi[16];
+};
+
+constexpr NibbleTables make_nibble_tables()
+{
+    NibbleTables t{};
+    for (int v = 0; v < 16; ++v) {
+        unsigned short a = 0, b = 0, c = 0;
+        for (const PairClass &pc : kPairClasses) {
+            if (pc.prev_hi & (1u << v)) a |= pc.bit;
+            if (pc.prev_lo & (1u << v)) b |= pc.bit;
+            if (pc.cur_hi & (1u << v)) c |= pc.bit;
+        }
+        t.prev_hi[v] = a;
+        t.prev_lo[v] = b;
+        t.cur_hi[v] = c;
+    }
+    return t;
+}
+
+// Product table, entry (p << 4) | (c >> 4): bit 0 = the pair breaks a rule,
+// bit 1 = both bytes are continuation bytes. Built at compile time from the
+// three nibble tables; each workgroup copies it into LDS.
+struct PairTable {
+    alignas(16) unsigned char e[4096];
+};
+
+constexpr PairTable make_pair_table()
+{
+    const NibbleTables t = make_nibble_tables();
+    PairTable p{};
+    for (unsigned int idx = 0; idx < 4096; ++idx) {
+        const unsigned int cls = t.prev_hi[idx >> 8] & t.prev_lo[(idx >> 4) & 15] & t.cur_hi[idx & 15];
+        p.e[idx] = (unsigned char)(((cls & ~kTwoConts) ? 1u : 0u) | ((cls & kTwoConts) ? 2u : 0u));
+    }
+    return p;
+}
+
+__device__ const PairTable g_pair_table = make_pair_table();
+
+// ------------------------------------------------------------ SWAR helpers
+// bit 7 of each byte of the result is set iff that byte of x is >= 0xE0 / 0xF0
+__device__ __forceinline__ unsigned int ge_e0(unsigned int x) { return x & (x << 1) & (x << 2) & 0x80808080u; }
+__device__ __forceinline__ unsigned int ge_f0(unsigned int x) { return ge_e0(x) & (x << 3); }
+// bit 7 of each byte set iff that byte is not a continuation byte (10xxxxxx)
+__device__ __forceinline__ unsigned int not_cont(unsigned int x)
+{
+    unsigned int y = (x & 0xC0C0C0C0u) ^ 0x80808080u;
+    return (y | (y << 1)) & 0x80808080u;
+}
+
+// 0xFF in every byte whose position 4k + b (b = 0..3) lies in [lo, hi)
+__device__ __forceinline__ unsigned int byte_range_mask(int k, unsigned int lo, unsigned int hi)
+{
+    unsigned int m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        unsigned int pos = 4 * k + b;
+        m |= (pos >= lo && pos < hi) ? (0xFFu << (8 * b)) : 0u;
+    }
+    return m;
+}
+
+// Decode the character whose lead byte is the low byte of w (little-endian
+// window of the next four bytes) into one UTF-16 word or a surrogate pair.
+// Bit layouts: section 3 (7/11/16/21 payload bits, most significant first;
+// values above U+FFFF become D800 | high ten bits, DC00 | low ten bits of
+// value - 0x10000). Returns the word count; garbage in -> garbage out.
+__device__ __forceinline__ int decode_utf8_char(unsigned int w, unsigned int *u0, unsigned int *u1)
+{
+    unsigned int b0 = w & 0xFFu;
+    unsigned int b1 = (w >> 8) & 0x3Fu, b2 = (w >> 16) & 0x3Fu, b3 = (w >> 24) & 0x3Fu;
+    unsigned int cp2 = ((b0 & 0x1Fu) << 6) | b1;
+    unsigned int cp3 = ((b0 & 0x0Fu) << 12) | (b1 << 6) | b2;
+    unsigned int cp4 = ((b0 & 0x07u) << 18) | (b1 << 12) | (b2 << 6) | b3;
+    unsigned int cp = b0 < 0x80u ? b0 : (b0 < 0xE0u ? cp2 : cp3);
+    unsigned int v = cp4 - 0x10000u;
+    bool pair = b0 >= 0xF0u;
+    *u0 = pair ? (0xD800u | ((v >> 10) & 0x3FFu)) : cp;
+    *u1 = 0xDC00u | (v & 0x3FFu);
+    return pair ? 2 : 1;
+}
+
+struct U8Dir {
+    using Out = unsigned short;                       // output code unit
+    static constexpr int kInUnit = 1;                 // bytes per input unit
+    static constexpr int kOutUnit = 2;                // bytes per output unit
+    static constexpr bool kNeedsTable = true;
+    static constexpr int kOpValidate = HU_OP_VALIDATE_UTF8;
+    static constexpr int kOpLength = HU_OP_UTF16_LENGTH_FROM_UTF8;
+    static constexpr int kOpConvert = HU_OP_CONVERT_UTF8_TO_UTF16LE;
+    // staging bound per 4 KiB sub-tile: valid input gives at most one word per
+    // byte plus one (a four-byte lead in the last byte)
+    static constexpr unsigned int kStageUnits = kSub + 40;
+
+    // x[0]: the 4 bytes before the chunk, x[1..4]: the chunk, x[5]: the 4
+    // bytes after. [lo, hi): positions of the chunk inside the input.
+    // `end_pos`: position of the input end relative to the chunk start if it
+    // falls in (0, 16], else a negative value.
+    // Returns the number of UTF-16 words of the characters that start in the
+    // chunk (if COUNT) and sets *flag to the first flagged position relative to
+    // the chunk start (kNoFlag if none).
+    template <bool COUNT>
+    __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], unsigned int lo, unsigned int hi,
+                                                           int end_pos, const unsigned char *table, int *flag)
+    {
+        unsigned int count = 0;
+        if (COUNT) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                unsigned int rm = byte_range_mask(k, lo, hi);
+                count += __popc(not_cont(x[k + 1]) & rm) + __popc(ge_f0(x[k + 1]) & rm);
+            }
+        }
+        int f = kNoFlag;
+        const bool ascii = ((x[1] | x[2] | x[3] | x[4]) & 0x80808080u) == 0;
+        if (!ascii || (x[0] & 0x80000000u) != 0) {
+            // An all-ASCII chunk can only be flagged if the byte just before
+            // it belongs to an unfinished character.
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                unsigned int cur = x[k + 1], prev = x[k];
+                unsigned int p1 = __builtin_amdgcn_alignbyte(cur, prev, 3);   // byte before each byte
+                unsigned int p2 = __builtin_amdgcn_alignbyte(cur, prev, 2);   // two before
+                unsigned int p3 = __builtin_amdgcn_alignbyte(cur, prev, 1);   // three before
+                unsigned int err = 0, two = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    unsigned int idx = (((p1 >> (8 * m)) & 0xFFu) << 4) | ((cur >> (8 * m + 4)) & 0xFu);
+                    unsigned int e = table[idx];
+                    err |= (e & 1u) << (8 * m + 7);
+                    two |= (e & 2u) << (8 * m + 6);
+                }
+                unsigned int must = ge_e0(p2) | ge_f0(p3);
+                unsigned int flags = (err | (two ^ must)) & byte_range_mask(k, lo, 32u);
+                if (flags && f == kNoFlag)
+                    f = 4 * k + (__builtin_ctz(flags) >> 3);
+            }
+        }
+        if (end_pos > 0) {
+            // truncation: a lead among the last three bytes that needs more
+            // bytes than remain (bytes before the chunk come from x[0])
+#pragma unroll
+            for (int back = 3; back >= 1; --back) {
+                // bytes outside the input read as zero and never match
+                const int j = end_pos - back;   // >= -2
+                const int i = j + 4;            // index into the 24 bytes of x[0..5]
+                const unsigned int dw = i < 4 ? x[0] : i < 8 ? x[1] : i < 12 ? x[2] : i < 16 ? x[3] : x[4];
+                const unsigned int b = (dw >> (8 * (i & 3))) & 0xFFu;
+                const unsigned int need = b >= 0xF0u ? 4u : b >= 0xE0u ? 3u : b >= 0xC0u ? 2u : 1u;
+                if (need > (unsigned int)back) {
+                    if (j < f)
+                        f = j;
+                    break;
+                }
+            }
+        }
+        *flag = f;
+        return count;
+    }
+
+    // Writes the words of the characters that start in the chunk to out[o..],
+    // dropping any that would land at or past `limit`.
+    __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
+                                                unsigned int o, unsigned int limit)
+    {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            unsigned int l = not_cont(x[k + 1]) & byte_range_mask(k, lo, hi);
+            while (l) {
+                unsigned int m = __builtin_ctz(l) >> 3;
+                l &= l - 1;
+                unsigned int w = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], m);
+                unsigned int u0, u1;
+                int nw = decode_utf8_char(w, &u0, &u1);
+                if (o + 1 < limit) {
+                    out[o] = (Out)u0;
+                    if (nw == 2)
+                        out[o + 1] = (Out)u1;
+                }
+                o += nw;
+            }
+        }
+    }
+};
+
+}  // namespace hu

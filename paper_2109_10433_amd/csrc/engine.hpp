@@ -123,11 +123,21 @@ __device__ __forceinline__ void chunk_range(const Doc &d, unsigned long long cv,
         hi = lo;
 }
 
+// A tile whose chunks all lie inside the input with the input end beyond them
+// takes the FULL path (no per-byte range checks, no end-of-input check).
+template <int U>
+__device__ __forceinline__ bool tile_is_interior(const Doc &d, unsigned long long tile)
+{
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    return tv >= d.off_b && tv + (unsigned long long)U * kSub < d.end_b;
+}
+
 // Validation and counting of a staged tile. Returns the per-chunk counts in
 // c[] and lowers flag_min to the first flagged input byte position.
-template <class Dir, int U, bool COUNT>
-__device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
-                                             unsigned long long tile, unsigned int c[U], unsigned long long &flag_min)
+template <class Dir, int U, bool COUNT, bool FULL>
+__device__ __forceinline__ void analyze_tile_as(const unsigned int *in, const unsigned char *table, const Doc &d,
+                                                unsigned long long tile, unsigned int c[U],
+                                                unsigned long long &flag_min)
 {
     const unsigned long long tv = tile * (unsigned long long)(U * kSub);
 #pragma unroll
@@ -135,11 +145,14 @@ __device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsig
         unsigned int x[6];
         read_chunk(in, u, x);
         const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
-        unsigned int lo, hi;
-        chunk_range<Dir>(d, cv, lo, hi);
-        const int end_pos = (cv < d.end_b && cv + kChunk >= d.end_b) ? (int)(d.end_b - cv) : -1;
+        unsigned int lo = 0, hi = kChunk / Dir::kInUnit;
+        int end_pos = -1;
+        if (!FULL) {
+            chunk_range<Dir>(d, cv, lo, hi);
+            end_pos = (cv < d.end_b && cv + kChunk >= d.end_b) ? (int)(d.end_b - cv) : -1;
+        }
         int f;
-        c[u] = Dir::template analyze<COUNT>(x, lo, hi, end_pos, table, &f);
+        c[u] = Dir::template analyze<COUNT, FULL>(x, lo, hi, end_pos, table, &f);
         if (f != kNoFlag) {
             const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
             flag_min = pos < flag_min ? pos : flag_min;
@@ -147,6 +160,16 @@ __device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsig
         // keep sub-tiles from being interleaved by the scheduler (register pressure)
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+template <class Dir, int U, bool COUNT>
+__device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
+                                             unsigned long long tile, unsigned int c[U], unsigned long long &flag_min)
+{
+    if (tile_is_interior<U>(d, tile))
+        analyze_tile_as<Dir, U, COUNT, true>(in, table, d, tile, c, flag_min);
+    else
+        analyze_tile_as<Dir, U, COUNT, false>(in, table, d, tile, c, flag_min);
 }
 
 // Exclusive offsets of every thread's count for each of U sub-tiles, and the
@@ -268,6 +291,36 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
     workgroup_exit(my_total, my_flag, s.red, c, hdr, status, status_cap, out, &s.flag, MODE == kLength);
 }
 
+// Output phase of a convert tile: per sub-tile, chunks decode into LDS at
+// their offsets (shifted so that LDS and global addresses agree modulo 16),
+// then the sub-tile's output leaves in aligned 16-byte stores.
+template <class Dir, int U, bool FULL>
+__device__ __forceinline__ void emit_tile(const unsigned int *in, typename Dir::Out *stage, const Doc &d,
+                                          unsigned long long tile, const unsigned int excl[U], const unsigned int tot[U],
+                                          unsigned long long pos, typename Dir::Out *dst)
+{
+    using Out = typename Dir::Out;
+    // output units between dst and the 16-byte aligned address below it
+    const unsigned int dst_mis = (unsigned int)(((uintptr_t)d.dst & 15u) / sizeof(Out));
+    constexpr unsigned int G = 16 / sizeof(Out);
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
+        unsigned int x[6];
+        read_chunk(in, u, x);
+        unsigned int lo = 0, hi = kChunk / Dir::kInUnit;
+        if (!FULL)
+            chunk_range<Dir>(d, tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk, lo, hi);
+        Dir::template emit<FULL>(x, lo, hi, stage, shift + excl[u], Dir::kStageUnits);
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        copy_out<Dir>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
+        __syncthreads();
+        pos += tot[u];
+    }
+}
+
 // ------------------------------------------------------------ convert
 // One workgroup per tile, tile = blockIdx.x. A tile only waits (in the
 // look-back) for tiles with smaller ids; workgroups are dispatched in id order
@@ -332,23 +385,10 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
         finish_call(call, hdr, pos + agg, status, status_cap, out, &s.red[0]);
 
     Out *dst = reinterpret_cast<Out *>(d.dst);
-    // output units between dst and the 16-byte aligned address below it
-    const unsigned int dst_mis = (unsigned int)(((uintptr_t)d.dst & 15u) / sizeof(Out));
-    constexpr unsigned int G = 16 / sizeof(Out);
-    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
-        unsigned int x[6];
-        read_chunk(s.in, u, x);
-        unsigned int lo, hi;
-        chunk_range<Dir>(d, tv + (unsigned long long)u * kSub + (unsigned long long)tid * kChunk, lo, hi);
-        Dir::emit(x, lo, hi, s.out, shift + excl[u], Dir::kStageUnits);
-        __syncthreads();
-        copy_out<Dir>(s.out, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
-        __syncthreads();
-        pos += tot[u];
-    }
+    if (tile_is_interior<U>(d, tile))
+        emit_tile<Dir, U, true>(s.in, s.out, d, tile, excl, tot, pos, dst);
+    else
+        emit_tile<Dir, U, false>(s.in, s.out, d, tile, excl, tot, pos, dst);
     if (tile == n_tiles - 1)
         wrap_clear(status, status_cap, &s.red[0]);
 }

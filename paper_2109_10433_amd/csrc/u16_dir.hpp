@@ -48,7 +48,7 @@ struct U16Dir {
 
     // [lo, hi): word positions of the chunk inside the input. Positions in
     // the flag are in words relative to the chunk start.
-    template <bool COUNT>
+    template <bool COUNT, bool FULL>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], unsigned int lo, unsigned int hi,
                                                            int /*end_pos*/, const unsigned char * /*table*/, int *flag)
     {
@@ -57,7 +57,7 @@ struct U16Dir {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j), pw = word(x, j - 1), nw = word(x, j + 1);
-            const bool in = (unsigned int)j >= lo && (unsigned int)j < hi;
+            const bool in = FULL || ((unsigned int)j >= lo && (unsigned int)j < hi);
             const bool bad = (is_high(w) && !is_low(nw)) || (is_low(w) && !is_high(pw));
             if (in && bad && f == kNoFlag)
                 f = j;
@@ -68,13 +68,14 @@ struct U16Dir {
         return count;
     }
 
+    template <bool FULL>
     __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
                                                 unsigned int o, unsigned int limit)
     {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j), nw = word(x, j + 1);
-            const unsigned int m = ((unsigned int)j >= lo && (unsigned int)j < hi) ? utf8_bytes_of(w) : 0u;
+            const unsigned int m = (FULL || ((unsigned int)j >= lo && (unsigned int)j < hi)) ? utf8_bytes_of(w) : 0u;
             unsigned int b0, b1 = 0, b2 = 0, b3 = 0;
             if (m == 4) {
                 const unsigned int cp = 0x10000u + (((w & 0x3FFu) << 10) | (nw & 0x3FFu));

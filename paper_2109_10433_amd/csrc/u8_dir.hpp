@@ -71,9 +71,10 @@ constexpr NibbleTables make_nibble_tables()
     return t;
 }
 
-// Product table, entry (p << 4) | (c >> 4): bit 0 = the pair breaks a rule,
-// bit 1 = both bytes are continuation bytes. Built at compile time from the
-// three nibble tables; each workgroup copies it into LDS.
+// Product table, entry (p << 4) | (c >> 4): bit 7 = the pair breaks a rule,
+// bit 6 = both bytes are continuation bytes (bit positions chosen so that four
+// entries packed into a dword line up with the per-byte SWAR masks). Built at
+// compile time from the three nibble tables; each workgroup copies it into LDS.
 struct PairTable {
     alignas(16) unsigned char e[4096];
 };
@@ -84,7 +85,7 @@ constexpr PairTable make_pair_table()
     PairTable p{};
     for (unsigned int idx = 0; idx < 4096; ++idx) {
         const unsigned int cls = t.prev_hi[idx >> 8] & t.prev_lo[(idx >> 4) & 15] & t.cur_hi[idx & 15];
-        p.e[idx] = (unsigned char)(((cls & ~kTwoConts) ? 1u : 0u) | ((cls & kTwoConts) ? 2u : 0u));
+        p.e[idx] = (unsigned char)(((cls & ~kTwoConts) ? 0x80u : 0u) | ((cls & kTwoConts) ? 0x40u : 0u));
     }
     return p;
 }
@@ -147,22 +148,30 @@ struct U8Dir {
     static constexpr unsigned int kStageUnits = kSub + 40;
 
     // x[0]: the 4 bytes before the chunk, x[1..4]: the chunk, x[5]: the 4
-    // bytes after. [lo, hi): positions of the chunk inside the input.
-    // `end_pos`: position of the input end relative to the chunk start if it
-    // falls in (0, 16], else a negative value.
-    // Returns the number of UTF-16 words of the characters that start in the
-    // chunk (if COUNT) and sets *flag to the first flagged position relative to
-    // the chunk start (kNoFlag if none).
-    template <bool COUNT>
+    // bytes after. FULL: the whole chunk and its neighbours lie inside the
+    // input (then lo = 0, hi = 16, no end inside). Otherwise [lo, hi) are the
+    // positions of the chunk inside the input and `end_pos` is the position of
+    // the input end relative to the chunk start if it falls in (0, 16], else
+    // negative. Returns the number of UTF-16 words of the characters that
+    // start in the chunk (if COUNT) and sets *flag to the first flagged
+    // position relative to the chunk start (kNoFlag if none).
+    template <bool COUNT, bool FULL>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], unsigned int lo, unsigned int hi,
                                                            int end_pos, const unsigned char *table, int *flag)
     {
+        // per dword: bytes >= E0 and >= F0 (bit 7 of each byte)
+        unsigned int G[5], F[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            G[k] = ge_e0(x[k]);
+            F[k] = G[k] & (x[k] << 3);
+        }
         unsigned int count = 0;
         if (COUNT) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                unsigned int rm = byte_range_mask(k, lo, hi);
-                count += __popc(not_cont(x[k + 1]) & rm) + __popc(ge_f0(x[k + 1]) & rm);
+                const unsigned int rm = FULL ? 0xFFFFFFFFu : byte_range_mask(k, lo, hi);
+                count += __popc(not_cont(x[k + 1]) & rm) + __popc(F[k + 1] & rm);
             }
         }
         int f = kNoFlag;
@@ -172,25 +181,28 @@ struct U8Dir {
             // it belongs to an unfinished character.
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                unsigned int cur = x[k + 1], prev = x[k];
-                unsigned int p1 = __builtin_amdgcn_alignbyte(cur, prev, 3);   // byte before each byte
-                unsigned int p2 = __builtin_amdgcn_alignbyte(cur, prev, 2);   // two before
-                unsigned int p3 = __builtin_amdgcn_alignbyte(cur, prev, 1);   // three before
-                unsigned int err = 0, two = 0;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    unsigned int idx = (((p1 >> (8 * m)) & 0xFFu) << 4) | ((cur >> (8 * m + 4)) & 0xFu);
-                    unsigned int e = table[idx];
-                    err |= (e & 1u) << (8 * m + 7);
-                    two |= (e & 2u) << (8 * m + 6);
-                }
-                unsigned int must = ge_e0(p2) | ge_f0(p3);
-                unsigned int flags = (err | (two ^ must)) & byte_range_mask(k, lo, 32u);
+                const unsigned int cur = x[k + 1], prev = x[k];
+                const unsigned int p1 = __builtin_amdgcn_alignbyte(cur, prev, 3);   // byte before each byte
+                // table index of byte m: (p1_m << 4) | (cur_m >> 4), from the
+                // 16-bit pair (p1_m << 8) | cur_m
+                const unsigned int y01 = __builtin_amdgcn_perm(p1, cur, 0x05010400u);   // [c0 p0 c1 p1]
+                const unsigned int y23 = __builtin_amdgcn_perm(p1, cur, 0x07030602u);   // [c2 p2 c3 p3]
+                const unsigned int i0 = (y01 & 0xFFFFu) >> 4, i1 = y01 >> 20;
+                const unsigned int i2 = (y23 & 0xFFFFu) >> 4, i3 = y23 >> 20;
+                const unsigned int e = (unsigned int)table[i0] | ((unsigned int)table[i1] << 8) |
+                                       ((unsigned int)table[i2] << 16) | ((unsigned int)table[i3] << 24);
+                // a continuation byte is required exactly where the byte two
+                // back is E0..FF or the byte three back is F0..FF
+                const unsigned int must = __builtin_amdgcn_alignbyte(G[k + 1], G[k], 2) |
+                                          __builtin_amdgcn_alignbyte(F[k + 1], F[k], 1);
+                unsigned int flags = (e | ((e << 1) ^ must)) & 0x80808080u;
+                if (!FULL)
+                    flags &= byte_range_mask(k, lo, 32u);
                 if (flags && f == kNoFlag)
                     f = 4 * k + (__builtin_ctz(flags) >> 3);
             }
         }
-        if (end_pos > 0) {
+        if (!FULL && end_pos > 0) {
             // truncation: a lead among the last three bytes that needs more
             // bytes than remain (bytes before the chunk come from x[0])
 #pragma unroll
@@ -214,12 +226,57 @@ struct U8Dir {
 
     // Writes the words of the characters that start in the chunk to out[o..],
     // dropping any that would land at or past `limit`.
+    template <bool FULL>
     __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
                                                 unsigned int o, unsigned int limit)
     {
+        unsigned int lead[4];
+        bool wide = false;   // a byte >= E0: three- or four-byte characters
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            unsigned int l = not_cont(x[k + 1]) & byte_range_mask(k, lo, hi);
+            lead[k] = not_cont(x[k + 1]) & (FULL ? 0xFFFFFFFFu : byte_range_mask(k, lo, hi));
+            wide |= (ge_e0(x[k + 1]) & lead[k]) != 0;
+        }
+        if (!__any(wide)) {
+            // Only one- and two-byte characters in this wave (the first case
+            // of the paper's core component, Algorithm "core component"): the
+            // word at a lead byte b with next byte n is b (b < 0x80) or
+            // ((b & 0x1F) << 6) | (n & 0x3F), computed for two positions per
+            // register in 16-bit halves; leads are placed by a masked popcount.
+            unsigned int base = o;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned int a = x[k + 1];
+                const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);   // next bytes
+                unsigned int w[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
+                    const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
+                    const unsigned int n2 = __builtin_amdgcn_perm(0u, n, sel);
+                    const unsigned int two = ((a2 & 0x001F001Fu) << 6) | (n2 & 0x003F003Fu);
+                    const unsigned int hi_bit = (a2 >> 7) & 0x00010001u;      // 1 where b >= 0x80
+                    const unsigned int m = hi_bit * 0xFFFFu;
+                    w[h] = (two & m) | (a2 & ~m);
+                }
+                const unsigned int l = lead[k];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (l & (0x80u << (8 * b))) {
+                        const unsigned int r = base + __popc(l & ((1u << (8 * b)) - 1u));
+                        if (r < limit) {
+                            const unsigned int wb = w[b >> 1];
+                            out[r] = (Out)((b & 1) ? (wb >> 16) : (wb & 0xFFFFu));
+                        }
+                    }
+                }
+                base += __popc(l);
+            }
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            unsigned int l = lead[k];
             while (l) {
                 unsigned int m = __builtin_ctz(l) >> 3;
                 l &= l - 1;

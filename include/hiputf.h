@@ -151,6 +151,75 @@ int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *
                                   size_t dst_cap_bytes, hu_result *d_result,
                                   void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many documents of any lengths, each with its own operation (any of
+ * the six, directions may be mixed), in one call of four kernel launches and
+ * no host synchronisation; safe to record into a HIP graph and replay (the
+ * document table and inputs are read on the device at run time).
+ * All pointers except `tuning` are device pointers.
+ * ---------------------------------------------------------------------- */
+
+/* One document (40 bytes). Input: src_base + src_off, n_units code units
+ * (bytes for UTF-8 operations, 2-byte aligned words for UTF-16 ones). Output
+ * (convert operations): dst_base + dst_off, capacity dst_cap output code
+ * units. Output regions must not overlap. */
+typedef struct {
+    uint64_t src_off;
+    uint64_t n_units;
+    uint64_t dst_off;
+    uint64_t dst_cap;
+    uint32_t op;          /* HU_OP_* */
+    uint32_t reserved;    /* 0 */
+} hu_doc;
+
+/* Launch shape of the batch kernels (see hu_tune_batch). */
+typedef struct {
+    uint32_t sub_tiles;       /* 4 KiB input sub-tiles per work item: 1, 2 or 4 (0 = default) */
+    uint32_t groups_per_cu;   /* workgroups per compute unit for the run kernels (0 = as many as fit) */
+} hu_tuning;
+
+/* Workspace bytes for a batch of n_docs documents whose inputs total at most
+ * total_input_bytes bytes (UTF-16 inputs count 2 bytes per word). */
+size_t hu_batch_workspace_bytes(uint32_t n_docs, uint64_t total_input_bytes);
+
+/* Runs the batch. results[d] receives document d's result with the same
+ * meaning as the single-buffer call of its operation. ws: device workspace of
+ * at least hu_batch_workspace_bytes(n_docs, total_input_bytes) bytes,
+ * 256-byte aligned, zero-filled before first use; each call leaves it ready
+ * for the next. If the documents need more work items than the workspace was
+ * sized for, every document reports HU_ERR_INVALID_ARGUMENT. A document with
+ * invalid arguments (misaligned UTF-16 input, unknown op, ...) reports
+ * HU_ERR_INVALID_ARGUMENT alone. tuning: host pointer or NULL.
+ * Returns HU_OK once enqueued, else HU_ERR_INVALID_ARGUMENT or HU_ERR_DEVICE. */
+int hu_batch_run(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                 void *dst_base, hu_result *results, const hu_tuning *tuning, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* Records one hu_batch_run into a HIP graph and instantiates it; *graph_exec
+ * receives a hipGraphExec_t. Replays (hu_graph_launch) read the document
+ * table, inputs and workspace at the same addresses, so callers may rewrite
+ * them in place between replays (same n_docs). */
+int hu_batch_graph_create(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                          void *dst_base, hu_result *results, const hu_tuning *tuning, void *ws, size_t ws_bytes,
+                          void **graph_exec);
+int hu_graph_launch(void *graph_exec, void *stream);
+void hu_graph_destroy(void *graph_exec);
+
+/* Autotuner: times hu_batch_run on the given batch (which it runs several
+ * times) for every sub_tiles in {1, 2, 4} and groups_per_cu in {1, 2, 4, 0},
+ * writes the fastest to *best and its mean time in microseconds to *best_us.
+ * If `key` is non-NULL and the environment variable HIPUTF_TUNE_CACHE names a
+ * file, the result is appended to that file as one JSON line
+ * {"key": ..., "device": ..., "cus": ..., "sub_tiles": ..., "groups_per_cu": ..., "us": ...}. */
+int hu_tune_batch(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                  void *dst_base, hu_result *results, void *ws, size_t ws_bytes, const char *key,
+                  hu_tuning *best, double *best_us, void *stream);
+
+/* Reads the last cached tuning stored under `key` for the current device from
+ * HIPUTF_TUNE_CACHE. Returns HU_OK and fills *out, or HU_ERR_INVALID_ARGUMENT
+ * when there is no such entry. */
+int hu_tuning_lookup(const char *key, hu_tuning *out);
+
 /* Library-wide: a human-readable name for an error code (static string). */
 const char *hu_error_name(int error);
 

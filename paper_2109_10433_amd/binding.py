@@ -72,12 +72,30 @@ lib.hu_workspace_bytes.argtypes = [_i, _sz]
 lib.hu_workspace_bytes.restype = _sz
 lib.hu_workspace_init.argtypes = [_p, _sz, _p]
 lib.hu_workspace_init.restype = _i
+lib.hu_batch_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint64]
+lib.hu_batch_workspace_bytes.restype = _sz
+lib.hu_batch_run.argtypes = [_p, ctypes.c_uint32, ctypes.c_uint64, _p, _p, _p, _p, _p, _sz, _p]
+lib.hu_batch_run.restype = _i
+lib.hu_batch_graph_create.argtypes = [_p, ctypes.c_uint32, ctypes.c_uint64, _p, _p, _p, _p, _p, _sz,
+                                      ctypes.POINTER(ctypes.c_void_p)]
+lib.hu_batch_graph_create.restype = _i
+lib.hu_graph_launch.argtypes = [_p, _p]
+lib.hu_graph_launch.restype = _i
+lib.hu_graph_destroy.argtypes = [_p]
+lib.hu_graph_destroy.restype = None
+lib.hu_tune_batch.argtypes = [_p, ctypes.c_uint32, ctypes.c_uint64, _p, _p, _p, _p, _sz, ctypes.c_char_p, _p,
+                              ctypes.POINTER(ctypes.c_double), _p]
+lib.hu_tune_batch.restype = _i
+lib.hu_tuning_lookup.argtypes = [ctypes.c_char_p, _p]
+lib.hu_tuning_lookup.restype = _i
 lib.hu_error_name.argtypes = [_i]
 lib.hu_error_name.restype = ctypes.c_char_p
 lib.hu_shutdown.argtypes = []
 lib.hu_shutdown.restype = None
 
-EXPORTED = [
+EXPORTED_BATCH = ["hu_batch_workspace_bytes", "hu_batch_run", "hu_batch_graph_create", "hu_graph_launch",
+                  "hu_graph_destroy", "hu_tune_batch", "hu_tuning_lookup"]
+EXPORTED = EXPORTED_BATCH + [
     "validate_utf8", "utf16_length_from_utf8", "convert_utf8_to_utf16le",
     "validate_utf16le", "utf8_length_from_utf16le", "convert_utf16le_to_utf8",
     "validate_utf8_async", "utf16_length_from_utf8_async", "convert_utf8_to_utf16le_async",
@@ -184,3 +202,101 @@ def result_from_device(rec: torch.Tensor) -> Result:
     b = rec.cpu().numpy().tobytes()[:16]
     r = HuResult.from_buffer_copy(b)
     return _res(r)
+
+
+# ---------------------------------------------------------------- batches
+
+class HuTuning(ctypes.Structure):
+    _fields_ = [("sub_tiles", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32)]
+
+
+try:
+    import numpy as _np
+    DOC_DTYPE = _np.dtype([("src_off", "<u8"), ("n_units", "<u8"), ("dst_off", "<u8"), ("dst_cap", "<u8"),
+                           ("op", "<u4"), ("reserved", "<u4")])
+except ImportError:  # pragma: no cover
+    DOC_DTYPE = None
+
+
+class Batch:
+    """A document table on the device plus its workspace and result records.
+
+    docs: numpy array of DOC_DTYPE (offsets into src / dst). src, dst: device
+    tensors holding all inputs / outputs (dst may be None without convert
+    operations)."""
+
+    def __init__(self, docs, src: torch.Tensor, dst: torch.Tensor | None = None,
+                 total_input_bytes: int | None = None):
+        import numpy as np
+        self.docs_host = np.ascontiguousarray(docs, dtype=DOC_DTYPE)
+        self.n = int(self.docs_host.size)
+        self.device = src.device
+        self.src = src
+        self.dst = dst
+        if total_input_bytes is None:
+            unit = np.where(self.docs_host["op"] >= OP_VALIDATE_UTF16LE, 2, 1).astype(np.uint64)
+            total_input_bytes = int((self.docs_host["n_units"] * unit).sum())
+        self.total = int(total_input_bytes)
+        self.docs = torch.from_numpy(self.docs_host.view(np.uint8).copy()).to(self.device)
+        self.results = torch.zeros((max(self.n, 1), 16), dtype=torch.uint8, device=self.device)
+        nbytes = int(lib.hu_batch_workspace_bytes(self.n, self.total))
+        self.ws = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws_ptr, self.ws_bytes = workspace_ptr(self.ws)
+
+    def update_docs(self, docs):
+        """Rewrite the device document table in place (same count)."""
+        import numpy as np
+        d = np.ascontiguousarray(docs, dtype=DOC_DTYPE)
+        assert d.size == self.n
+        self.docs.copy_(torch.from_numpy(d.view(np.uint8).copy()).to(self.device))
+        self.docs_host = d
+
+    def _args(self):
+        return (self.docs.data_ptr(), self.n, self.total, self.src.data_ptr(),
+                self.dst.data_ptr() if self.dst is not None else None, self.results.data_ptr())
+
+    def run(self, tuning: HuTuning | None = None, stream=None) -> int:
+        a = self._args()
+        return lib.hu_batch_run(*a, ctypes.byref(tuning) if tuning is not None else None,
+                                self.ws_ptr, self.ws_bytes, stream_handle(stream))
+
+    def graph(self, tuning: HuTuning | None = None):
+        a = self._args()
+        h = ctypes.c_void_p()
+        rc = lib.hu_batch_graph_create(*a, ctypes.byref(tuning) if tuning is not None else None,
+                                       self.ws_ptr, self.ws_bytes, ctypes.byref(h))
+        if rc != OK:
+            raise RuntimeError(f"graph capture failed: {error_name(rc)}")
+        return h
+
+    def tune(self, key: str | None = None, stream=None):
+        a = self._args()
+        best = HuTuning()
+        us = ctypes.c_double()
+        rc = lib.hu_tune_batch(*a, self.ws_ptr, self.ws_bytes, key.encode() if key else None,
+                               ctypes.byref(best), ctypes.byref(us), stream_handle(stream))
+        if rc != OK:
+            raise RuntimeError(f"tuning failed: {error_name(rc)}")
+        return best, us.value
+
+    def results_host(self):
+        """(errors int32 array, counts uint64 array) after synchronising."""
+        import numpy as np
+        torch.cuda.synchronize(self.device)
+        h = self.results[: self.n].cpu().numpy().reshape(-1).view(np.uint8)
+        rec = h.view([("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
+        return rec["error"].copy(), rec["count"].copy()
+
+
+def graph_launch(handle, stream=None) -> int:
+    return lib.hu_graph_launch(handle, stream_handle(stream))
+
+
+def graph_destroy(handle) -> None:
+    lib.hu_graph_destroy(handle)
+
+
+def tuning_lookup(key: str):
+    t = HuTuning()
+    rc = lib.hu_tuning_lookup(key.encode(), ctypes.byref(t))
+    return t if rc == OK else None

@@ -1,0 +1,247 @@
+// batch.hpp - many documents, any of the six operations each, in one call.
+//
+// Three steps, all on the device (nothing is read back, so a call can be
+// recorded into a HIP graph and replayed with new document tables):
+//   plan: one workgroup gives every document its tiles (work items): a scan
+//         over the documents' tile counts, UTF-8 documents first, then
+//         UTF-16 ones; documents with no input or invalid arguments get their
+//         result here. It also advances the workspace epoch.
+//   fill: item -> document map.
+//   run:  one persistent kernel per input encoding walks its items with a
+//         fixed stride (workgroup w takes items w, w + G, ...). An item only
+//         waits (look-back) for earlier items of its own document; items are
+//         taken in increasing order by every workgroup and workgroups are
+//         dispatched in order, so the lowest unfinished item always has a
+//         running owner. Each document has its own look-back chain and error
+//         key; the workgroup that runs a document's last tile writes its
+//         result.
+#pragma once
+
+#include "engine.hpp"
+
+namespace hu {
+
+struct BatchDoc {                     // mirrors hu_doc
+    unsigned long long src_off, n_units, dst_off, dst_cap;
+    unsigned int op, reserved;
+};
+static_assert(sizeof(BatchDoc) == sizeof(hu_doc), "hu_doc layout");
+
+struct BatchWs {
+    WsHeader *hdr;                    // pad[0]: UTF-8 items, pad[1]: UTF-16 items
+    unsigned int *first_item;         // per document
+    unsigned long long *err;          // per document error key
+    unsigned int *item_map;           // per item: document index
+    unsigned long long *status;       // per item look-back status
+    unsigned long long item_cap;
+};
+
+__device__ __forceinline__ bool op_is_u16(unsigned int op) { return op >= HU_OP_VALIDATE_UTF16LE; }
+__device__ __forceinline__ int op_mode(unsigned int op) { return (int)(op % 3u); }   // kValidate/kLength/kConvert
+
+__device__ __forceinline__ Doc make_doc(const BatchDoc &b, const uint8_t *src_base, uint8_t *dst_base)
+{
+    const uint8_t *src = src_base + b.src_off;
+    const unsigned long long bytes = op_is_u16(b.op) ? 2 * b.n_units : b.n_units;
+    Doc d;
+    d.base = (const uint8_t *)((uintptr_t)src & ~(uintptr_t)15);
+    d.off_b = (unsigned long long)((uintptr_t)src & 15u);
+    d.end_b = d.off_b + bytes;
+    d.n = b.n_units;
+    d.dst = dst_base ? (void *)(dst_base + b.dst_off) : nullptr;
+    d.cap = b.dst_cap;
+    return d;
+}
+
+// 0 when the document is fine, else the error its result carries.
+__device__ __forceinline__ int doc_check(const BatchDoc &b, const uint8_t *src_base, const uint8_t *dst_base)
+{
+    if (b.op > HU_OP_CONVERT_UTF16LE_TO_UTF8 || b.n_units > (1ull << 38))
+        return HU_ERR_INVALID_ARGUMENT;
+    if (b.n_units == 0)
+        return 0;
+    const uintptr_t src = (uintptr_t)(src_base + b.src_off);
+    if (src_base == nullptr || (op_is_u16(b.op) && (src & 1u)))
+        return HU_ERR_INVALID_ARGUMENT;
+    if (op_mode(b.op) == kConvert && b.dst_cap > 0) {
+        if (dst_base == nullptr)
+            return HU_ERR_INVALID_ARGUMENT;
+        if (b.op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)(dst_base + b.dst_off) & 1u))
+            return HU_ERR_INVALID_ARGUMENT;
+    }
+    return 0;
+}
+
+__device__ __forceinline__ unsigned long long doc_tiles(const BatchDoc &b, const uint8_t *src_base,
+                                                        unsigned long long tile_bytes)
+{
+    if (b.n_units == 0)
+        return 0;
+    const unsigned long long off = (unsigned long long)((uintptr_t)(src_base + b.src_off) & 15u);
+    const unsigned long long bytes = op_is_u16(b.op) ? 2 * b.n_units : b.n_units;
+    return (off + bytes + tile_bytes - 1) / tile_bytes;
+}
+
+constexpr int kPlanBlock = 1024;
+
+// Exclusive prefix over a 1024-thread workgroup of two counters at once.
+__device__ __forceinline__ void plan_scan2(unsigned long long a, unsigned long long b, unsigned long long *ea,
+                                           unsigned long long *eb, unsigned long long *ta, unsigned long long *tb,
+                                           unsigned long long (*s_tmp)[kPlanBlock / 64])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    unsigned long long ia = a, ib = b;
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long ua = __shfl_up(ia, d, 64), ub = __shfl_up(ib, d, 64);
+        if (lane >= d) {
+            ia += ua;
+            ib += ub;
+        }
+    }
+    if (lane == 63) {
+        s_tmp[0][wave] = ia;
+        s_tmp[1][wave] = ib;
+    }
+    __syncthreads();
+    unsigned long long pa = 0, pb = 0, sa = 0, sb = 0;
+    for (int w = 0; w < kPlanBlock / 64; ++w) {
+        const unsigned long long xa = s_tmp[0][w], xb = s_tmp[1][w];
+        if (w < wave) {
+            pa += xa;
+            pb += xb;
+        }
+        sa += xa;
+        sb += xb;
+    }
+    *ea = pa + ia - a;
+    *eb = pb + ib - b;
+    *ta = sa;
+    *tb = sb;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kPlanBlock) void k_batch_plan(const BatchDoc *docs, unsigned int n_docs,
+                                                           const uint8_t *src_base, const uint8_t *dst_base,
+                                                           hu_result *results, BatchWs w,
+                                                           unsigned long long tile_bytes)
+{
+    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ int s_wrap;
+    const unsigned int per = (n_docs + kPlanBlock - 1) / kPlanBlock;
+    const unsigned int d0 = threadIdx.x * per;
+    const unsigned int d1 = min(d0 + per, n_docs);
+    unsigned long long c8 = 0, c16 = 0;
+    for (unsigned int d = d0; d < d1; ++d) {
+        const BatchDoc b = docs[d];
+        if (doc_check(b, src_base, dst_base) == 0) {
+            const unsigned long long t = doc_tiles(b, src_base, tile_bytes);
+            if (op_is_u16(b.op))
+                c16 += t;
+            else
+                c8 += t;
+        }
+    }
+    unsigned long long e8, e16, t8, t16;
+    plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);
+    const bool overflow = t8 + t16 > w.item_cap;
+    for (unsigned int d = d0; d < d1; ++d) {
+        const BatchDoc b = docs[d];
+        int err = doc_check(b, src_base, dst_base);
+        if (err == 0 && overflow)
+            err = HU_ERR_INVALID_ARGUMENT;   // work-item capacity of the workspace exceeded
+        const unsigned long long t = err ? 0 : doc_tiles(b, src_base, tile_bytes);
+        if (t == 0) {
+            hu_result r;
+            r.error = err;
+            r.reserved = 0;
+            r.count = 0;
+            results[d] = r;
+            w.first_item[d] = 0xFFFFFFFFu;
+            continue;
+        }
+        if (op_is_u16(b.op)) {
+            w.first_item[d] = (unsigned int)(t8 + e16);
+            e16 += t;
+        } else {
+            w.first_item[d] = (unsigned int)e8;
+            e8 += t;
+        }
+    }
+    if (threadIdx.x == 0) {
+        w.hdr->pad[0] = overflow ? 0 : t8;
+        w.hdr->pad[1] = overflow ? 0 : t16;
+        w.hdr->hang = 0;
+        const unsigned int e = (w.hdr->epoch + 1u) & kEpochMask;
+        w.hdr->epoch = e;
+        s_wrap = e == 0;
+    }
+    __syncthreads();
+    if (s_wrap) {
+        for (unsigned long long i = threadIdx.x; i < w.item_cap; i += kPlanBlock)
+            w.status[i] = 0;
+    }
+}
+
+__global__ void k_batch_fill(const BatchDoc *docs, unsigned int n_docs, const uint8_t *src_base, BatchWs w,
+                             unsigned long long tile_bytes)
+{
+    for (unsigned int d = blockIdx.x * blockDim.x + threadIdx.x; d < n_docs; d += gridDim.x * blockDim.x) {
+        const unsigned int first = w.first_item[d];
+        if (first == 0xFFFFFFFFu)
+            continue;
+        const unsigned long long t = doc_tiles(docs[d], src_base, tile_bytes);
+        for (unsigned long long k = 0; k < t; ++k)
+            w.item_map[first + k] = d;
+    }
+}
+
+template <class Dir, int U>
+__device__ __forceinline__ void batch_run_body(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_base,
+                                               hu_result *results, BatchWs w)
+{
+    __shared__ ConvertShared<Dir, U> s;
+    constexpr bool kU16 = Dir::kInUnit == 2;
+    if (Dir::kNeedsTable)
+        build_pair_table(s.table);
+    const unsigned int epoch = w.hdr->epoch;
+    const unsigned long long n8 = w.hdr->pad[0], n16 = w.hdr->pad[1];
+    const unsigned long long lo = kU16 ? n8 : 0ull, hi = kU16 ? n8 + n16 : n8;
+    const unsigned long long tile_bytes = (unsigned long long)U * kSub;
+    for (unsigned long long i = lo + blockIdx.x; i < hi; i += gridDim.x) {
+        const unsigned int di = w.item_map[i];
+        const BatchDoc b = docs[di];
+        const unsigned long long first = w.first_item[di];
+        const Doc d = make_doc(b, src_base, dst_base);
+        const unsigned long long n_tiles = doc_tiles(b, src_base, tile_bytes);
+        const Chain cx{w.status, first, i, epoch, &w.err[di], &w.hdr->hang};
+        const CallInfo call{d.base + d.off_b, d.n, d.cap, (int)b.op};
+        auto fin = [&](unsigned long long total) {
+            const unsigned long long key = __hip_atomic_load(&w.err[di], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned int hang = __hip_atomic_load(&w.hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            results[di] = result_from(call, key, hang, total);
+            w.err[di] = 0;
+        };
+        switch (op_mode(b.op)) {
+        case kValidate: chained_tile<Dir, U, kValidate>(s, d, i - first, n_tiles, cx, fin); break;
+        case kLength: chained_tile<Dir, U, kLength>(s, d, i - first, n_tiles, cx, fin); break;
+        default: chained_tile<Dir, U, kConvert>(s, d, i - first, n_tiles, cx, fin); break;
+        }
+        __syncthreads();
+    }
+}
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_batch_run_u8(const BatchDoc *docs, const uint8_t *src_base,
+                                                         uint8_t *dst_base, hu_result *results, BatchWs w)
+{
+    batch_run_body<U8Dir, U>(docs, src_base, dst_base, results, w);
+}
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_batch_run_u16(const BatchDoc *docs, const uint8_t *src_base,
+                                                          uint8_t *dst_base, hu_result *results, BatchWs w)
+{
+    batch_run_body<U16Dir, U>(docs, src_base, dst_base, results, w);
+}
+
+}  // namespace hu

@@ -321,6 +321,71 @@ __device__ __forceinline__ void emit_tile(const unsigned int *in, typename Dir::
     }
 }
 
+// ------------------------------------------------------------ chained tiles
+// Where a tile sits in a look-back chain: one chain per document.
+struct Chain {
+    unsigned long long *status;      // status words, indexed by item
+    unsigned long long first;        // item index of the document's first tile
+    unsigned long long item;         // item index of this tile
+    unsigned int epoch;
+    unsigned long long *err_key;     // the document's error key
+    unsigned int *hang;
+};
+
+// One tile of a document in a look-back chain: load, validate, count, scan,
+// publish, look back; thread 0 of the document's last tile then calls
+// fin(total output units); in convert mode the tile's output is written.
+// The pair table must already be in s.table. All threads must call.
+template <class Dir, int U, int MODE, class Finisher>
+__device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc &d, unsigned long long tile,
+                                             unsigned long long n_tiles, const Chain &cx, Finisher fin)
+{
+    using Out = typename Dir::Out;
+    const int tid = threadIdx.x;
+    uint4 q[U], pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
+    load_tile<U>(d, tile, q, pre, post);
+    stage_tile<U>(s.in, d, tile, q, pre, post);
+    __syncthreads();
+
+    unsigned long long my_flag = ~0ull;
+    unsigned int c[U];
+    analyze_tile<Dir, U, MODE != kValidate>(s.in, s.table, d, tile, c, my_flag);
+    const unsigned long long tile_flag = block_min_u64(my_flag, s.red);
+    unsigned int excl[U], tot[U];
+    block_scan_multi<U>(c, excl, tot, s.scan);
+    unsigned int agg = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        agg += tot[u];
+    const bool first = cx.item == cx.first;
+    if (tid == 0) {
+        if (tile_flag != ~0ull)
+            report_flag(cx.err_key, tile_flag);
+        publish(&cx.status[cx.item], pack_status(cx.epoch, first ? kFlagInclusive : kFlagAggregate, agg));
+    }
+    if (tid < 64) {
+        unsigned long long excl_tile = 0;
+        if (!first)
+            excl_tile = lookback(cx.status, (long long)cx.first, (long long)cx.item, cx.epoch, cx.hang);
+        if (tid == 0) {
+            if (!first)
+                publish(&cx.status[cx.item], pack_status(cx.epoch, kFlagInclusive, excl_tile + agg));
+            s.prefix = excl_tile;
+        }
+    }
+    __syncthreads();
+    const unsigned long long pos = s.prefix;   // output units before this tile
+    if (tile == n_tiles - 1 && tid == 0)
+        fin(pos + agg);
+    if (MODE == kConvert) {
+        Out *dst = reinterpret_cast<Out *>(d.dst);
+        if (tile_is_interior<U>(d, tile))
+            emit_tile<Dir, U, true>(s.in, s.out, d, tile, excl, tot, pos, dst);
+        else
+            emit_tile<Dir, U, false>(s.in, s.out, d, tile, excl, tot, pos, dst);
+    }
+}
+
 // ------------------------------------------------------------ convert
 // One workgroup per tile, tile = blockIdx.x. A tile only waits (in the
 // look-back) for tiles with smaller ids; workgroups are dispatched in id order
@@ -334,61 +399,24 @@ template <class Dir, int U>
 __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                              unsigned long long *status, unsigned long long status_cap, hu_result *out)
 {
-    using Out = typename Dir::Out;
     __shared__ ConvertShared<Dir, U> s;
-    const int tid = threadIdx.x;
     const unsigned long long tile = blockIdx.x;
     const CallInfo call{d.base + d.off_b, d.n, d.cap, Dir::kOpConvert};
     if (n_tiles == 0) {
-        if (tid == 0)
+        if (threadIdx.x == 0)
             finish_call(call, hdr, 0ull, status, status_cap, out, &s.red[0]);
         __syncthreads();
         wrap_clear(status, status_cap, &s.red[0]);
         return;
     }
-    uint4 q[U], pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
-    load_tile<U>(d, tile, q, pre, post);
     if (Dir::kNeedsTable)
         build_pair_table(s.table);
     const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    stage_tile<U>(s.in, d, tile, q, pre, post);
-    __syncthreads();
-
-    unsigned long long my_flag = ~0ull;
-    unsigned int c[U];
-    analyze_tile<Dir, U, true>(s.in, s.table, d, tile, c, my_flag);
-    const unsigned long long tile_flag = block_min_u64(my_flag, s.red);
-    unsigned int excl[U], tot[U];
-    block_scan_multi<U>(c, excl, tot, s.scan);
-    unsigned int agg = 0;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        agg += tot[u];
-    if (tid == 0) {
-        if (tile_flag != ~0ull)
-            report_flag(hdr, tile_flag);
-        publish(&status[tile], pack_status(epoch, tile == 0 ? kFlagInclusive : kFlagAggregate, agg));
-    }
-    if (tid < 64) {
-        unsigned long long excl_tile = 0;
-        if (tile != 0)
-            excl_tile = lookback(status, 0, (long long)tile, epoch, &hdr->hang);
-        if (tid == 0) {
-            if (tile != 0)
-                publish(&status[tile], pack_status(epoch, kFlagInclusive, excl_tile + agg));
-            s.prefix = excl_tile;
-        }
-    }
-    __syncthreads();
-    unsigned long long pos = s.prefix;   // output units before this sub-tile
-    if (tile == n_tiles - 1 && tid == 0)
-        finish_call(call, hdr, pos + agg, status, status_cap, out, &s.red[0]);
-
-    Out *dst = reinterpret_cast<Out *>(d.dst);
-    if (tile_is_interior<U>(d, tile))
-        emit_tile<Dir, U, true>(s.in, s.out, d, tile, excl, tot, pos, dst);
-    else
-        emit_tile<Dir, U, false>(s.in, s.out, d, tile, excl, tot, pos, dst);
+    const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang};
+    unsigned long long *s_wrap = &s.red[0];
+    chained_tile<Dir, U, kConvert>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
+        finish_call(call, hdr, total, status, status_cap, out, s_wrap);
+    });
     if (tile == n_tiles - 1)
         wrap_clear(status, status_cap, &s.red[0]);
 }

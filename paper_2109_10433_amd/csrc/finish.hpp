@@ -74,11 +74,11 @@ struct CallInfo {
     int op;                      // HU_OP_*
 };
 
-// Result of the call from the workspace header and the output total.
-__device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr, unsigned long long total)
+// Result of a call (or of one document of a batch) from its error key, the
+// hang flag and the output total.
+__device__ inline hu_result result_from(const CallInfo &c, unsigned long long key, unsigned int hang,
+                                        unsigned long long total)
 {
-    const unsigned long long key = __hip_atomic_load(&hdr->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned int hang = __hip_atomic_load(&hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     hu_result r;
     r.reserved = 0;
     if (hang) {
@@ -106,11 +106,18 @@ __device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr, unsign
     return r;
 }
 
+__device__ inline hu_result call_result(const CallInfo &c, WsHeader *hdr, unsigned long long total)
+{
+    const unsigned long long key = __hip_atomic_load(&hdr->err_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned int hang = __hip_atomic_load(&hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return result_from(c, key, hang, total);
+}
+
 // Report a flagged position (smallest wins) and wait until the report has
 // landed, so that a status word published afterwards implies it.
-__device__ inline void report_flag(WsHeader *hdr, unsigned long long pos)
+__device__ inline void report_flag(unsigned long long *err_key, unsigned long long pos)
 {
-    const unsigned long long old = atomicMax(&hdr->err_key, ~pos);
+    const unsigned long long old = atomicMax(err_key, ~pos);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     if (old == 0x5A5A5A5A5A5A5A5Aull)   // consumes the returned value (forces the wait)
         __builtin_amdgcn_s_sleep(1);

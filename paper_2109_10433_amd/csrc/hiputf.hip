@@ -5,12 +5,16 @@
 // the hu_result and resets the workspace for the next call (finish.hpp).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <utility>
 
+#include "batch.hpp"
 #include "hiputf.h"
-#include "engine.hpp"
 
 namespace hu {
 
@@ -130,6 +134,126 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     if (hipLaunchKernel(kc.fn, dim3(grid), dim3(kBlock), args, 0, stream) != hipSuccess)
         return HU_ERR_DEVICE;
     return HU_OK;
+}
+
+// ------------------------------------------------------------ batches
+constexpr unsigned int kBatchDefaultU = 2;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+    size_t first, err, map, status, total;
+    unsigned long long item_cap;
+};
+
+BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
+{
+    BatchLayout l;
+    // the smallest tile is one 4 KiB sub-tile; each document adds at most two
+    // partial tiles (alignment offset and tail)
+    l.item_cap = total_input_bytes / kSub + 2ull * n_docs + 1;
+    l.first = kHeaderBytes;
+    l.err = align256(l.first + 4ull * n_docs);
+    l.map = align256(l.err + 8ull * n_docs);
+    l.status = align256(l.map + 4ull * l.item_cap);
+    l.total = align256(l.status + 8ull * l.item_cap);
+    return l;
+}
+
+const void *batch_run_kernel(bool u16, unsigned int U)
+{
+#define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
+    if (!u16)
+        return U == 1 ? HU_K(k_batch_run_u8<1>) : U == 2 ? HU_K(k_batch_run_u8<2>) : HU_K(k_batch_run_u8<4>);
+    return U == 1 ? HU_K(k_batch_run_u16<1>) : U == 2 ? HU_K(k_batch_run_u16<2>) : HU_K(k_batch_run_u16<4>);
+#undef HU_K
+}
+
+int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                  void *dst_base, hu_result *results, const hu_tuning *tuning, void *ws, size_t ws_bytes,
+                  hipStream_t stream)
+{
+    if (n_docs == 0)
+        return HU_OK;
+    if (docs == nullptr || results == nullptr || ws == nullptr || ((uintptr_t)ws & 255u) != 0)
+        return HU_ERR_INVALID_ARGUMENT;
+    const BatchLayout l = batch_layout(n_docs, total_input_bytes);
+    if (ws_bytes < l.total || l.item_cap >= 0xFFFFFFFFull)
+        return HU_ERR_INVALID_ARGUMENT;
+    const unsigned int U = (tuning && tuning->sub_tiles) ? tuning->sub_tiles : kBatchDefaultU;
+    if (U != 1 && U != 2 && U != 4)
+        return HU_ERR_INVALID_ARGUMENT;
+    char *base = reinterpret_cast<char *>(ws);
+    BatchWs w{reinterpret_cast<WsHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
+              reinterpret_cast<unsigned long long *>(base + l.err), reinterpret_cast<unsigned int *>(base + l.map),
+              reinterpret_cast<unsigned long long *>(base + l.status), l.item_cap};
+    const BatchDoc *bd = reinterpret_cast<const BatchDoc *>(docs);
+    const uint8_t *src = reinterpret_cast<const uint8_t *>(src_base);
+    uint8_t *dst = reinterpret_cast<uint8_t *>(dst_base);
+    const unsigned long long tile_bytes = (unsigned long long)U * kSub;
+
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanBlock), 0, stream, bd, n_docs, src, (const uint8_t *)dst,
+                       results, w, tile_bytes);
+    const unsigned int fill_grid = (n_docs + 255) / 256 < 2048 ? (n_docs + 255) / 256 : 2048;
+    hipLaunchKernelGGL(k_batch_fill, dim3(fill_grid), dim3(256), 0, stream, bd, n_docs, src, w, tile_bytes);
+    for (int dir = 0; dir < 2; ++dir) {
+        const void *fn = batch_run_kernel(dir == 1, U);
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess)
+            return HU_ERR_DEVICE;
+        const int max_blocks = max_resident_blocks(fn);
+        if (max_blocks <= 0)
+            return HU_ERR_DEVICE;
+        int cus = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_info_mu);
+            cus = g_info[dev].cus;
+        }
+        const int per_cu = cus > 0 ? max_blocks / cus : 1;
+        const unsigned int gpc = (tuning && tuning->groups_per_cu) ? tuning->groups_per_cu : (unsigned int)per_cu;
+        const unsigned int grid = (unsigned int)(cus * (int)(gpc < (unsigned int)per_cu ? gpc : per_cu));
+        void *args[] = {&bd, &src, &dst, &results, &w};
+        if (hipLaunchKernel(fn, dim3(grid ? grid : 1), dim3(kBlock), args, 0, stream) != hipSuccess)
+            return HU_ERR_DEVICE;
+    }
+    return hipGetLastError() == hipSuccess ? HU_OK : HU_ERR_DEVICE;
+}
+
+// ------------------------------------------------------------ tuning cache
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s/%d", prop.gcnArchName, prop.multiProcessorCount);
+    for (char *c = buf; *c; ++c)
+        if (*c == '"' || *c == '\\')
+            *c = '_';
+    return buf;
+}
+
+// value of "name": in a JSON line written by tune_store (string or integer)
+bool json_field(const std::string &line, const char *name, std::string *out)
+{
+    const std::string pat = std::string("\"") + name + "\": ";
+    size_t p = line.find(pat);
+    if (p == std::string::npos)
+        return false;
+    p += pat.size();
+    if (p < line.size() && line[p] == '"') {
+        const size_t q = line.find('"', p + 1);
+        if (q == std::string::npos)
+            return false;
+        *out = line.substr(p + 1, q - p - 1);
+        return true;
+    }
+    size_t q = p;
+    while (q < line.size() && line[q] != ',' && line[q] != '}')
+        ++q;
+    *out = line.substr(p, q - p);
+    return true;
 }
 
 // ------------------------------------------------------------ synchronous path
@@ -310,6 +434,154 @@ int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *
 {
     return hu::enqueue(HU_OP_CONVERT_UTF16LE_TO_UTF8, src, n_words, dst, dst_cap_bytes, d_result, ws, ws_bytes,
                        (hipStream_t)stream);
+}
+
+size_t hu_batch_workspace_bytes(uint32_t n_docs, uint64_t total_input_bytes)
+{
+    return hu::batch_layout(n_docs, total_input_bytes).total;
+}
+
+int hu_batch_run(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                 void *dst_base, hu_result *results, const hu_tuning *tuning, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::batch_enqueue(docs, n_docs, total_input_bytes, src_base, dst_base, results, tuning, ws, ws_bytes,
+                             (hipStream_t)stream);
+}
+
+int hu_batch_graph_create(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                          void *dst_base, hu_result *results, const hu_tuning *tuning, void *ws, size_t ws_bytes,
+                          void **graph_exec)
+{
+    if (graph_exec == nullptr)
+        return HU_ERR_INVALID_ARGUMENT;
+    *graph_exec = nullptr;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return HU_ERR_DEVICE;
+    int rc = HU_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = HU_ERR_DEVICE;
+    } else {
+        rc = hu::batch_enqueue(docs, n_docs, total_input_bytes, src_base, dst_base, results, tuning, ws, ws_bytes, s);
+        if (hipStreamEndCapture(s, &g) != hipSuccess && rc == HU_OK)
+            rc = HU_ERR_DEVICE;
+    }
+    if (rc == HU_OK && g != nullptr) {
+        hipGraphExec_t e = nullptr;
+        if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess)
+            rc = HU_ERR_DEVICE;
+        else
+            *graph_exec = (void *)e;
+    }
+    if (g != nullptr)
+        (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+
+int hu_graph_launch(void *graph_exec, void *stream)
+{
+    if (graph_exec == nullptr)
+        return HU_ERR_INVALID_ARGUMENT;
+    return hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream) == hipSuccess ? HU_OK : HU_ERR_DEVICE;
+}
+
+void hu_graph_destroy(void *graph_exec)
+{
+    if (graph_exec != nullptr)
+        (void)hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+}
+
+int hu_tune_batch(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
+                  void *dst_base, hu_result *results, void *ws, size_t ws_bytes, const char *key, hu_tuning *best,
+                  double *best_us, void *stream)
+{
+    if (best == nullptr || best_us == nullptr)
+        return HU_ERR_INVALID_ARGUMENT;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return HU_ERR_DEVICE;
+    const unsigned int subs[] = {1, 2, 4};
+    const unsigned int gpcs[] = {1, 2, 4, 0};
+    const int reps = 3;
+    double best_t = 1e300;
+    hu_tuning bt{hu::kBatchDefaultU, 0};
+    int rc = HU_OK;
+    for (unsigned int u : subs) {
+        for (unsigned int g : gpcs) {
+            const hu_tuning t{u, g};
+            rc = hu::batch_enqueue(docs, n_docs, total_input_bytes, src_base, dst_base, results, &t, ws, ws_bytes, st);
+            if (rc != HU_OK)
+                break;
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps && rc == HU_OK; ++r)
+                rc = hu::batch_enqueue(docs, n_docs, total_input_bytes, src_base, dst_base, results, &t, ws, ws_bytes,
+                                       st);
+            (void)hipEventRecord(e1, st);
+            float ms = 0.f;
+            if (rc != HU_OK || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = rc != HU_OK ? rc : HU_ERR_DEVICE;
+                break;
+            }
+            const double us = 1000.0 * ms / reps;
+            if (us < best_t) {
+                best_t = us;
+                bt = t;
+            }
+        }
+        if (rc != HU_OK)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != HU_OK)
+        return rc;
+    *best = bt;
+    *best_us = best_t;
+    const char *path = std::getenv("HIPUTF_TUNE_CACHE");
+    if (key != nullptr && path != nullptr && *path) {
+        std::string k(key);
+        for (char &c : k)
+            if (c == '"' || c == '\\')
+                c = '_';
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "{\"key\": \"%s\", \"device\": \"%s\", \"sub_tiles\": %u, \"groups_per_cu\": %u, \"us\": %.3f}\n",
+                         k.c_str(), hu::device_tag().c_str(), bt.sub_tiles, bt.groups_per_cu, best_t);
+            std::fclose(f);
+        }
+    }
+    return HU_OK;
+}
+
+int hu_tuning_lookup(const char *key, hu_tuning *out)
+{
+    const char *path = std::getenv("HIPUTF_TUNE_CACHE");
+    if (key == nullptr || out == nullptr || path == nullptr || !*path)
+        return HU_ERR_INVALID_ARGUMENT;
+    FILE *f = std::fopen(path, "r");
+    if (f == nullptr)
+        return HU_ERR_INVALID_ARGUMENT;
+    const std::string dev = hu::device_tag();
+    char buf[1024];
+    bool found = false;
+    hu_tuning t{0, 0};
+    while (std::fgets(buf, sizeof buf, f)) {
+        const std::string line(buf);
+        std::string k, d, su, gp;
+        if (hu::json_field(line, "key", &k) && hu::json_field(line, "device", &d) && k == key && d == dev &&
+            hu::json_field(line, "sub_tiles", &su) && hu::json_field(line, "groups_per_cu", &gp)) {
+            t.sub_tiles = (uint32_t)std::strtoul(su.c_str(), nullptr, 10);
+            t.groups_per_cu = (uint32_t)std::strtoul(gp.c_str(), nullptr, 10);
+            found = true;   // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    if (!found || (t.sub_tiles != 1 && t.sub_tiles != 2 && t.sub_tiles != 4))
+        return HU_ERR_INVALID_ARGUMENT;
+    *out = t;
+    return HU_OK;
 }
 
 const char *hu_error_name(int error)

@@ -183,15 +183,22 @@ __device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsign
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < U; i += 2) {
-        const unsigned int v = c[i] | (c[i + 1] << 16);
-        const unsigned int inc = wave_inclusive_sum(v);
-        if (lane == 63) {
-            s_scan[i][wave] = inc & 0xFFFFu;
-            s_scan[i + 1][wave] = inc >> 16;
+        if (i + 1 < U) {
+            const unsigned int v = c[i] | (c[i + 1] << 16);
+            const unsigned int inc = wave_inclusive_sum(v);
+            if (lane == 63) {
+                s_scan[i][wave] = inc & 0xFFFFu;
+                s_scan[i + 1][wave] = inc >> 16;
+            }
+            const unsigned int e = inc - v;
+            excl[i] = e & 0xFFFFu;
+            excl[i + 1] = e >> 16;
+        } else {                       // odd U: the last sub-tile alone
+            const unsigned int inc = wave_inclusive_sum(c[i]);
+            if (lane == 63)
+                s_scan[i][wave] = inc;
+            excl[i] = inc - c[i];
         }
-        const unsigned int e = inc - v;
-        excl[i] = e & 0xFFFFu;
-        excl[i + 1] = e >> 16;
     }
     __syncthreads();
 #pragma unroll

@@ -60,7 +60,8 @@ def lay_out(items, rng):
         docs[i]["op"] = op
         if op in (2, 5):
             unit = 2 if op == 2 else 1
-            dpos += (int(rng.integers(0, 8)) * unit) if op == 5 else 2 * int(rng.integers(0, 8))
+            dpos += int(rng.integers(0, 8)) * unit
+            dpos += dpos & (unit - 1)          # UTF-16 output at an even offset
             docs[i]["dst_off"] = dpos
             docs[i]["dst_cap"] = cap
             dpos += cap * unit + 16
@@ -185,19 +186,29 @@ def test_batch_exhaustive_short_strings():
 def test_batch_invalid_arguments(texts):
     rng = np.random.default_rng(5)
     t8, t16 = texts
-    docs = np.zeros(4, dtype=hu.DOC_DTYPE)
+    docs = np.zeros(6, dtype=hu.DOC_DTYPE)
     src = torch.from_numpy(t8[:1000].copy()).cuda()
+    dst = torch.full((256,), 0xA5, dtype=torch.uint8, device="cuda")
     docs[0] = (1, 10, 0, 0, 3, 0)      # UTF-16 at an odd address
     docs[1] = (0, 10, 0, 0, 9, 0)      # unknown op
     docs[2] = (0, 100, 0, 0, 0, 0)     # fine
     docs[3] = (0, 0, 0, 0, 2, 0)       # empty convert
+    docs[4] = (0, 10, 1, 10, 2, 0)     # UTF-16 output at an odd address
+    docs[5] = (0, 10, 64, 10, 2, 0)    # fine
     say("batch invalid arguments")
-    b = hu.Batch(docs, src)
+    b = hu.Batch(docs, src, dst)
     assert b.run() == 0
     errs, counts = b.results_host()
     assert errs[0] == hu.INVALID_ARGUMENT and errs[1] == hu.INVALID_ARGUMENT
     assert (errs[2], counts[2]) == tuple(oracle.validate_utf8(t8[:100]))
     assert (errs[3], counts[3]) == (0, 0)
+    assert errs[4] == hu.INVALID_ARGUMENT
+    w, r = oracle.convert_utf8_to_utf16le(t8[:10], 10)
+    assert (errs[5], counts[5]) == (r.error, r.count)
+    out = dst.cpu().numpy()
+    assert np.all(out[:64] == 0xA5)
+    if r.error == 0:
+        assert np.array_equal(out[64:64 + w.nbytes], w.view(np.uint8))
     # a workspace sized for fewer work items than the documents need: every
     # document reports it (capacity for total 0 bytes is 2 items per document
     # + 1; two 60000-byte documents need 8 items each at 8 KiB tiles)

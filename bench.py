@@ -11,6 +11,14 @@ Inputs are resident in HBM before timing starts.
 `value` is the validating UTF-8 -> UTF-16LE throughput in GB/s of algorithmic
 bytes (input bytes read + output bytes written), aggregated over the four
 profiles, from HIP events around each launch on the launch stream.
+
+Two batched workloads are timed after the step loop, each against the same
+documents run as one launch per document (the plain path):
+  * 100 000 UTF-8 documents (log-normal lengths, median 2 KiB, 16 B - 1 MiB,
+    mixed profiles, 1% with one injected error) converted to UTF-16LE in one
+    batch call, with sub-tile count and workgroups per CU from the autotuner;
+  * 10 000 UTF-16LE documents (uniform 64 B - 4 MiB, mixed profiles, 0.5% with
+    an unpaired surrogate) converted to UTF-8 by replaying a captured HIP graph.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -46,6 +54,171 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _time_on_stream(fn, stream, reps):
+    """Mean seconds of fn() over reps calls, from HIP events on `stream`."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def _plain_launches(hu, fns, stream, passes):
+    """One library launch per document (fns: one callable each); mean seconds
+    per pass over all documents, HIP events on the stream."""
+    def one_pass():
+        for f in fns:
+            rc = f()
+            if rc != 0:
+                raise RuntimeError(f"per-document launch failed: {hu.error_name(rc)}")
+    one_pass()
+    return _time_on_stream(one_pass, stream, passes)
+
+
+def bench_utf8_documents(args, hu, wl, dev, stream):
+    """100k UTF-8 documents -> UTF-16LE: autotuned batch vs per-document launches."""
+    import numpy as np
+    import torch
+    t_gen = time.time()
+    b = wl.utf8_documents(n_docs=args.docs8, pool_bytes=32 * wl.MIB)
+    n = b.offsets.size - 1
+    lens = np.diff(b.offsets).astype(np.uint64)
+    total = int(b.offsets[-1])
+    src = torch.from_numpy(b.data).to(dev)
+    dst = torch.zeros(2 * total + 64, dtype=torch.uint8, device=dev)
+    docs = np.zeros(n, dtype=hu.DOC_DTYPE)
+    docs["src_off"] = b.offsets[:-1]
+    docs["n_units"] = lens
+    docs["dst_off"] = 2 * b.offsets[:-1]
+    docs["dst_cap"] = lens
+    docs["op"] = hu.OP_CONVERT_UTF8_TO_UTF16LE
+    batch = hu.Batch(docs, src, dst)
+    log(f"utf8 documents: {n} docs, {total} B, generated in {time.time() - t_gen:.1f}s")
+    best, best_us = batch.tune(f"utf8-documents-{n}", stream)
+    log(f"utf8 documents: tuned sub_tiles={best.sub_tiles} groups_per_cu={best.groups_per_cu} ({best_us:.0f} us)")
+
+    t_batch = _time_on_stream(lambda: batch.run(best, stream), stream, args.steps)
+    errs, counts = batch.results_host()
+    bad = errs != 0
+    if not np.array_equal(bad, b.injected):
+        raise RuntimeError("utf8 documents: documents with errors differ from the injected set")
+    out_bytes = int(2 * counts[~bad].sum())
+
+    # plain: one async convert launch per document, results to their own records
+    recs = torch.zeros((n, 16), dtype=torch.uint8, device=dev)
+    ws = hu.workspace(hu.OP_CONVERT_UTF8_TO_UTF16LE, int(lens.max()), dev)
+    wsp, wsb = hu.workspace_ptr(ws)
+    sh = hu.stream_handle(stream)
+    sp, dp, rp = src.data_ptr(), dst.data_ptr(), recs.data_ptr()
+    f = hu.lib.convert_utf8_to_utf16le_async
+    offs = [int(x) for x in b.offsets[:-1]]
+    ls = [int(x) for x in lens]
+    fns = [(lambda i=i: f(sp + offs[i], ls[i], dp + 2 * offs[i], ls[i], rp + 16 * i, wsp, wsb, sh)) for i in range(n)]
+    t_plain = _plain_launches(hu, fns, stream, args.plain_passes)
+    torch.cuda.synchronize()
+    h = recs.cpu().numpy().reshape(-1).view([("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
+    if not (np.array_equal(h["error"], errs) and np.array_equal(h["count"], counts)):
+        raise RuntimeError("utf8 documents: batched and per-document results differ")
+    algo = total + out_bytes
+    return {
+        "workload": f"{n} UTF-8 documents -> UTF-16LE, log-normal lengths (median 2 KiB, 16 B-1 MiB), "
+                    f"mixed profiles, 1% injected errors",
+        "docs": n, "input_bytes": total, "docs_with_errors": int(bad.sum()),
+        "tuning": {"sub_tiles": best.sub_tiles, "groups_per_cu": best.groups_per_cu, "tile_bytes": 4096 * best.sub_tiles},
+        "batched": {"ms": round(t_batch * 1e3, 3), "docs_per_s": round(n / t_batch, 1),
+                    "GBps": round(algo / t_batch / 1e9, 1)},
+        "plain_per_document_launches": {"ms": round(t_plain * 1e3, 3), "docs_per_s": round(n / t_plain, 1),
+                                        "GBps": round(algo / t_plain / 1e9, 2)},
+        "speedup_batched_vs_plain": round(t_plain / t_batch, 1),
+    }
+
+
+def bench_utf16_documents(args, hu, wl, dev, stream):
+    """10k UTF-16LE documents -> UTF-8: graph-replayed tuned batch vs per-document launches."""
+    import numpy as np
+    import torch
+    t_gen = time.time()
+    spec = wl.utf16_document_spec(n_docs=args.docs16, pool_bytes=32 * wl.MIB)
+    n = spec.length.size
+    offs = spec.offsets
+    total_w = int(offs[-1])
+    # assemble the batch on the device from the profile pools
+    pools = [torch.from_numpy(t.u16.view(np.int16).copy()).to(dev) for t in spec.pools]
+    src = torch.empty(total_w + 32, dtype=torch.int16, device=dev)
+    for d in range(n):
+        a, l = int(spec.start[d]), int(spec.length[d])
+        src[int(offs[d]):int(offs[d]) + l].copy_(pools[spec.profiles[d]][a:a + l])
+    inj = np.nonzero(spec.injected)[0]
+    for d in inj:
+        p = int(offs[d] + spec.inj_pos[d])
+        src[p] = int(np.int16(spec.inj_words[d, 0].view(np.int16)))
+        if spec.inj_pos[d] + 1 < spec.length[d]:
+            src[p + 1] = int(spec.inj_words[d, 1].view(np.int16))
+    del pools
+    # exact output capacity for clean documents, 3 bytes per word otherwise
+    expect = np.array([spec.utf8_bytes(d) if not spec.injected[d] else 0 for d in range(n)], dtype=np.uint64)
+    cap = np.where(spec.injected, 3 * spec.length, expect).astype(np.uint64)
+    dst_off = np.concatenate([[0], np.cumsum(cap)])[:-1].astype(np.uint64)
+    dst = torch.zeros(int(cap.sum()) + 64, dtype=torch.uint8, device=dev)
+    docs = np.zeros(n, dtype=hu.DOC_DTYPE)
+    docs["src_off"] = 2 * offs[:-1]
+    docs["n_units"] = spec.length
+    docs["dst_off"] = dst_off
+    docs["dst_cap"] = cap
+    docs["op"] = hu.OP_CONVERT_UTF16LE_TO_UTF8
+    batch = hu.Batch(docs, src, dst)
+    log(f"utf16 documents: {n} docs, {2 * total_w} B, assembled in {time.time() - t_gen:.1f}s")
+    best, best_us = batch.tune(f"utf16-documents-{n}", stream)
+    log(f"utf16 documents: tuned sub_tiles={best.sub_tiles} groups_per_cu={best.groups_per_cu} ({best_us:.0f} us)")
+    g = batch.graph(best)
+    try:
+        hu.graph_launch(g, stream)
+        t_graph = _time_on_stream(lambda: hu.graph_launch(g, stream), stream, args.steps)
+    finally:
+        torch.cuda.synchronize()
+        hu.graph_destroy(g)
+    errs, counts = batch.results_host()
+    want_err = np.where(spec.injected, 7, 0)
+    want_cnt = np.where(spec.injected, 2 * np.maximum(spec.inj_pos, 0), expect).astype(np.uint64)
+    if not (np.array_equal(errs, want_err) and np.array_equal(counts, want_cnt)):
+        k = int(np.nonzero((errs != want_err) | (counts != want_cnt))[0][0])
+        raise RuntimeError(f"utf16 documents: doc {k}: {(errs[k], counts[k])} != {(want_err[k], want_cnt[k])}")
+    out_bytes = int(expect.sum())
+
+    recs = torch.zeros((n, 16), dtype=torch.uint8, device=dev)
+    ws = hu.workspace(hu.OP_CONVERT_UTF16LE_TO_UTF8, int(spec.length.max()), dev)
+    wsp, wsb = hu.workspace_ptr(ws)
+    sh = hu.stream_handle(stream)
+    sp, dp, rp = src.data_ptr(), dst.data_ptr(), recs.data_ptr()
+    f = hu.lib.convert_utf16le_to_utf8_async
+    so = [int(2 * x) for x in offs[:-1]]
+    ls = [int(x) for x in spec.length]
+    do = [int(x) for x in dst_off]
+    cp = [int(x) for x in cap]
+    fns = [(lambda i=i: f(sp + so[i], ls[i], dp + do[i], cp[i], rp + 16 * i, wsp, wsb, sh)) for i in range(n)]
+    t_plain = _plain_launches(hu, fns, stream, args.plain_passes)
+    torch.cuda.synchronize()
+    h = recs.cpu().numpy().reshape(-1).view([("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
+    if not (np.array_equal(h["error"], errs) and np.array_equal(h["count"], counts)):
+        raise RuntimeError("utf16 documents: batched and per-document results differ")
+    algo = 2 * total_w + out_bytes
+    return {
+        "workload": f"{n} UTF-16LE documents -> UTF-8, lengths uniform 64 B-4 MiB, mixed profiles, "
+                    f"0.5% unpaired surrogates, HIP graph replay",
+        "docs": n, "input_bytes": 2 * total_w, "docs_with_errors": int(spec.injected.sum()),
+        "tuning": {"sub_tiles": best.sub_tiles, "groups_per_cu": best.groups_per_cu, "tile_bytes": 4096 * best.sub_tiles},
+        "batched_graph": {"ms": round(t_graph * 1e3, 3), "docs_per_s": round(n / t_graph, 1),
+                          "GBps": round(algo / t_graph / 1e9, 1),
+                          "pct_peak": round(100 * algo / t_graph / 1e9 / PEAK_HBM_GBS, 1)},
+        "plain_per_document_launches": {"ms": round(t_plain * 1e3, 3), "docs_per_s": round(n / t_plain, 1),
+                                        "GBps": round(algo / t_plain / 1e9, 1)},
+        "speedup_batched_vs_plain": round(t_plain / t_graph, 2),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +228,10 @@ def main() -> int:
     ap.add_argument("--profiles", default="latin,cyrillic,cjk,emoji")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="comma list of ops to run (default all): u8u16,u16u8,len8,len16,val8,val16")
+    ap.add_argument("--no-batched", action="store_true", help="skip the two batched document workloads")
+    ap.add_argument("--docs8", type=int, default=100_000, help="UTF-8 documents in the batched workload")
+    ap.add_argument("--docs16", type=int, default=10_000, help="UTF-16LE documents in the batched workload")
+    ap.add_argument("--plain-passes", type=int, default=2, help="timed passes of the per-document launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build is single-GPU (got --gpus {args.gpus}); "
@@ -216,13 +393,24 @@ def main() -> int:
         else:
             traffic_note = "counters taken on other kernel sources: stale"
 
+    # ---------------------------------------------------------------- batched documents
+    batched = None
+    texts = {p: data[p]["text"] for p in profiles}
+    if not args.no_batched:
+        del data, ws8, ws16, recs
+        torch.cuda.empty_cache()
+        batched = {"utf8_documents": bench_utf8_documents(args, hu, wl, dev, stream)}
+        torch.cuda.empty_cache()
+        batched["utf16_documents"] = bench_utf16_documents(args, hu, wl, dev, stream)
+        torch.cuda.empty_cache()
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
         cpu_bytes, cpu_t = 0, 0.0
         for p in profiles:
-            t = data[p]["text"]
+            t = texts[p]
             t1 = time.perf_counter()
             w, r = oracle.convert_utf8_to_utf16le(t.u8)
             cpu_t += time.perf_counter() - t1
@@ -252,6 +440,7 @@ def main() -> int:
                      "kernel": "k_convert_u8<4>", "traffic_note": traffic_note},
         "cpu_baseline": cpu,
         "copy_ceiling_GBps": round(copy_gbs, 1),
+        "batched": batched,
         "detail": detail,
         "kernel_sources": kernel_source_digest(),
     }

@@ -153,8 +153,10 @@ int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *
 
 /* ------------------------------------------------------------------------
  * Batches: many documents of any lengths, each with its own operation (any of
- * the six, directions may be mixed), in one call of four kernel launches and
- * no host synchronisation; safe to record into a HIP graph and replay (the
+ * the six, directions may be mixed), in one call of three kernel launches
+ * (plan, item map, one fused run kernel with one workgroup per work item;
+ * the run kernel takes one more launch per 2^24 - 1 work items) and no host
+ * synchronisation; safe to record into a HIP graph and replay (the
  * document table and inputs are read on the device at run time).
  * All pointers except `tuning` are device pointers.
  * ---------------------------------------------------------------------- */
@@ -175,7 +177,8 @@ typedef struct {
 /* Launch shape of the batch kernels (see hu_tune_batch). */
 typedef struct {
     uint32_t sub_tiles;       /* 4 KiB input sub-tiles per work item: 1, 2 or 4 (0 = default) */
-    uint32_t groups_per_cu;   /* workgroups per compute unit for the run kernels (0 = as many as fit) */
+    uint32_t groups_per_cu;   /* at most this many run-kernel workgroups per compute unit, enforced by
+                                 reserving unused LDS (0 = as many as the kernel's resources allow) */
 } hu_tuning;
 
 /* Workspace bytes for a batch of n_docs documents whose inputs total at most
@@ -206,11 +209,11 @@ int hu_graph_launch(void *graph_exec, void *stream);
 void hu_graph_destroy(void *graph_exec);
 
 /* Autotuner: times hu_batch_run on the given batch (which it runs several
- * times) for every sub_tiles in {1, 2, 4} and groups_per_cu in {1, 2, 4, 0},
+ * times) for every sub_tiles in {1, 2, 4} and groups_per_cu in {2, 4, 6, 0},
  * writes the fastest to *best and its mean time in microseconds to *best_us.
  * If `key` is non-NULL and the environment variable HIPUTF_TUNE_CACHE names a
  * file, the result is appended to that file as one JSON line
- * {"key": ..., "device": ..., "cus": ..., "sub_tiles": ..., "groups_per_cu": ..., "us": ...}. */
+ * {"key": ..., "device": "<arch>/<compute units>", "sub_tiles": ..., "groups_per_cu": ..., "us": ...}. */
 int hu_tune_batch(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
                   void *dst_base, hu_result *results, void *ws, size_t ws_bytes, const char *key,
                   hu_tuning *best, double *best_us, void *stream);

@@ -6,15 +6,17 @@
 //         over the documents' tile counts, UTF-8 documents first, then
 //         UTF-16 ones; documents with no input or invalid arguments get their
 //         result here. It also advances the workspace epoch.
-//   fill: item -> document map.
-//   run:  one persistent kernel per input encoding walks its items with a
-//         fixed stride (workgroup w takes items w, w + G, ...). An item only
-//         waits (look-back) for earlier items of its own document; items are
-//         taken in increasing order by every workgroup and workgroups are
-//         dispatched in order, so the lowest unfinished item always has a
-//         running owner. Each document has its own look-back chain and error
-//         key; the workgroup that runs a document's last tile writes its
-//         result.
+//   fill: item -> (document, tile of the document) map.
+//   run:  one fused kernel for both input encodings, one workgroup per work
+//         item (workgroup b runs item base + b; the grids cover the host's
+//         upper bound on the item count, in as many launches as the grid size
+//         limit needs, and surplus workgroups leave at once). An item only
+//         waits (look-back) for earlier items of its own document, and
+//         workgroups are dispatched in id order, so the lowest unfinished
+//         item always has a running workgroup whose predecessors are done,
+//         however few workgroups the hardware holds at a time. Each document
+//         has its own look-back chain and error key; the workgroup that runs
+//         a document's last tile writes its result.
 #pragma once
 
 #include "engine.hpp"
@@ -31,7 +33,7 @@ struct BatchWs {
     WsHeader *hdr;                    // pad[0]: UTF-8 items, pad[1]: UTF-16 items
     unsigned int *first_item;         // per document
     unsigned long long *err;          // per document error key
-    unsigned int *item_map;           // per item: document index
+    unsigned long long *item_map;     // per item: document index | tile index << 32
     unsigned long long *status;       // per item look-back status
     unsigned long long item_cap;
 };
@@ -191,57 +193,62 @@ __global__ void k_batch_fill(const BatchDoc *docs, unsigned int n_docs, const ui
             continue;
         const unsigned long long t = doc_tiles(docs[d], src_base, tile_bytes);
         for (unsigned long long k = 0; k < t; ++k)
-            w.item_map[first + k] = d;
+            w.item_map[first + k] = (unsigned long long)d | (k << 32);
     }
 }
 
+// One work item (tile `tile` of document di, global item index i).
 template <class Dir, int U>
-__device__ __forceinline__ void batch_run_body(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_base,
-                                               hu_result *results, BatchWs w)
+__device__ __forceinline__ void batch_item(ConvertShared<Dir, U> &s, const BatchDoc &b, unsigned int di,
+                                           unsigned long long tile, unsigned long long i, unsigned int epoch,
+                                           const uint8_t *src_base, uint8_t *dst_base, hu_result *results, BatchWs w)
 {
-    __shared__ ConvertShared<Dir, U> s;
-    constexpr bool kU16 = Dir::kInUnit == 2;
     if (Dir::kNeedsTable)
         build_pair_table(s.table);
-    const unsigned int epoch = w.hdr->epoch;
-    const unsigned long long n8 = w.hdr->pad[0], n16 = w.hdr->pad[1];
-    const unsigned long long lo = kU16 ? n8 : 0ull, hi = kU16 ? n8 + n16 : n8;
-    const unsigned long long tile_bytes = (unsigned long long)U * kSub;
-    for (unsigned long long i = lo + blockIdx.x; i < hi; i += gridDim.x) {
-        const unsigned int di = w.item_map[i];
-        const BatchDoc b = docs[di];
-        const unsigned long long first = w.first_item[di];
-        const Doc d = make_doc(b, src_base, dst_base);
-        const unsigned long long n_tiles = doc_tiles(b, src_base, tile_bytes);
-        const Chain cx{w.status, first, i, epoch, &w.err[di], &w.hdr->hang};
-        const CallInfo call{d.base + d.off_b, d.n, d.cap, (int)b.op};
-        auto fin = [&](unsigned long long total) {
-            const unsigned long long key = __hip_atomic_load(&w.err[di], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned int hang = __hip_atomic_load(&w.hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            results[di] = result_from(call, key, hang, total);
-            w.err[di] = 0;
-        };
-        switch (op_mode(b.op)) {
-        case kValidate: chained_tile<Dir, U, kValidate>(s, d, i - first, n_tiles, cx, fin); break;
-        case kLength: chained_tile<Dir, U, kLength>(s, d, i - first, n_tiles, cx, fin); break;
-        default: chained_tile<Dir, U, kConvert>(s, d, i - first, n_tiles, cx, fin); break;
-        }
-        __syncthreads();
+    const Doc d = make_doc(b, src_base, dst_base);
+    const unsigned long long n_tiles = doc_tiles(b, src_base, (unsigned long long)U * kSub);
+    const Chain cx{w.status, i - tile, i, epoch, &w.err[di], &w.hdr->hang};
+    const CallInfo call{d.base + d.off_b, d.n, d.cap, (int)b.op};
+    auto fin = [&](unsigned long long total) {
+        const unsigned long long key = __hip_atomic_load(&w.err[di], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int hang = __hip_atomic_load(&w.hdr->hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        results[di] = result_from(call, key, hang, total);
+        w.err[di] = 0;
+    };
+    switch (op_mode(b.op)) {
+    case kValidate: chained_tile<Dir, U, kValidate>(s, d, tile, n_tiles, cx, fin); break;
+    case kLength: chained_tile<Dir, U, kLength>(s, d, tile, n_tiles, cx, fin); break;
+    default: chained_tile<Dir, U, kConvert>(s, d, tile, n_tiles, cx, fin); break;
     }
 }
 
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_batch_run_u8(const BatchDoc *docs, const uint8_t *src_base,
-                                                         uint8_t *dst_base, hu_result *results, BatchWs w)
-{
-    batch_run_body<U8Dir, U>(docs, src_base, dst_base, results, w);
-}
+union BatchShared {
+    ConvertShared<U8Dir, U> u8;
+    ConvertShared<U16Dir, U> u16;
+};
 
+// Items [0, n8) are UTF-8 input, [n8, n8 + n16) UTF-16LE. Dynamic LDS (unused)
+// may be requested at launch to cap the workgroups resident per CU.
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_batch_run_u16(const BatchDoc *docs, const uint8_t *src_base,
-                                                          uint8_t *dst_base, hu_result *results, BatchWs w)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_batch_run(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_base, hu_result *results, BatchWs w,
+                 unsigned long long item_base)
 {
-    batch_run_body<U16Dir, U>(docs, src_base, dst_base, results, w);
+    __shared__ BatchShared<U> s;
+    const unsigned long long i = item_base + blockIdx.x;
+    const unsigned long long n8 = w.hdr->pad[0], n16 = w.hdr->pad[1];
+    if (i >= n8 + n16)
+        return;
+    const unsigned long long m = w.item_map[i];
+    const unsigned int di = (unsigned int)m;
+    const unsigned long long tile = m >> 32;
+    const BatchDoc b = docs[di];
+    const unsigned int epoch = w.hdr->epoch;
+    if (i < n8)
+        batch_item<U8Dir, U>(s.u8, b, di, tile, i, epoch, src_base, dst_base, results, w);
+    else
+        batch_item<U16Dir, U>(s.u16, b, di, tile, i, epoch, src_base, dst_base, results, w);
 }
 
 }  // namespace hu

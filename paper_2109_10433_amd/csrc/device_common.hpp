@@ -125,6 +125,11 @@ __device__ unsigned long long lookback(unsigned long long *status, long long fir
                 }
                 return 0;
             }
+            // another wait already gave up: the call ends in a device error,
+            // so stop waiting too instead of spinning to the limit
+            if ((spins & 4095u) == 0 &&
+                __hip_atomic_load(hang_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                return 0;
             if (spins > 8)
                 __builtin_amdgcn_s_sleep(1);
             continue;

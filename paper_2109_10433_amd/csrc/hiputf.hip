@@ -155,18 +155,37 @@ BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
     l.first = kHeaderBytes;
     l.err = align256(l.first + 4ull * n_docs);
     l.map = align256(l.err + 8ull * n_docs);
-    l.status = align256(l.map + 4ull * l.item_cap);
+    l.status = align256(l.map + 8ull * l.item_cap);
     l.total = align256(l.status + 8ull * l.item_cap);
     return l;
 }
 
-const void *batch_run_kernel(bool u16, unsigned int U)
+const void *batch_run_kernel(unsigned int U)
 {
 #define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
-    if (!u16)
-        return U == 1 ? HU_K(k_batch_run_u8<1>) : U == 2 ? HU_K(k_batch_run_u8<2>) : HU_K(k_batch_run_u8<4>);
-    return U == 1 ? HU_K(k_batch_run_u16<1>) : U == 2 ? HU_K(k_batch_run_u16<2>) : HU_K(k_batch_run_u16<4>);
+    return U == 1 ? HU_K(k_batch_run<1>) : U == 2 ? HU_K(k_batch_run<2>) : HU_K(k_batch_run<4>);
 #undef HU_K
+}
+
+// Dynamic LDS that leaves room for at most `groups_per_cu` workgroups of the
+// kernel per CU (0: none requested, occupancy set by the kernel's resources).
+size_t lds_pad(const void *fn, unsigned int groups_per_cu)
+{
+    if (groups_per_cu == 0)
+        return 0;
+    int dev = 0, per_cu = 0, per_block = 0;
+    hipFuncAttributes fa;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&fa, fn) != hipSuccess || per_cu <= 0)
+        return 0;
+    const size_t fixed = fa.sharedSizeBytes;
+    size_t want = (size_t)per_cu / groups_per_cu;
+    want = want > 1024 ? want - 1024 : want;          // allocation granularity slack
+    if (want > (size_t)per_block)
+        want = (size_t)per_block;
+    return want > fixed ? want - fixed : 0;
 }
 
 int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_bytes, const void *src_base,
@@ -178,14 +197,15 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     if (docs == nullptr || results == nullptr || ws == nullptr || ((uintptr_t)ws & 255u) != 0)
         return HU_ERR_INVALID_ARGUMENT;
     const BatchLayout l = batch_layout(n_docs, total_input_bytes);
-    if (ws_bytes < l.total || l.item_cap >= 0xFFFFFFFFull)
+    if (ws_bytes < l.total || l.item_cap >= 0x7FFFFFFFull)
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned int U = (tuning && tuning->sub_tiles) ? tuning->sub_tiles : kBatchDefaultU;
     if (U != 1 && U != 2 && U != 4)
         return HU_ERR_INVALID_ARGUMENT;
     char *base = reinterpret_cast<char *>(ws);
     BatchWs w{reinterpret_cast<WsHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
-              reinterpret_cast<unsigned long long *>(base + l.err), reinterpret_cast<unsigned int *>(base + l.map),
+              reinterpret_cast<unsigned long long *>(base + l.err),
+              reinterpret_cast<unsigned long long *>(base + l.map),
               reinterpret_cast<unsigned long long *>(base + l.status), l.item_cap};
     const BatchDoc *bd = reinterpret_cast<const BatchDoc *>(docs);
     const uint8_t *src = reinterpret_cast<const uint8_t *>(src_base);
@@ -196,24 +216,17 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
                        results, w, tile_bytes);
     const unsigned int fill_grid = (n_docs + 255) / 256 < 2048 ? (n_docs + 255) / 256 : 2048;
     hipLaunchKernelGGL(k_batch_fill, dim3(fill_grid), dim3(256), 0, stream, bd, n_docs, src, w, tile_bytes);
-    for (int dir = 0; dir < 2; ++dir) {
-        const void *fn = batch_run_kernel(dir == 1, U);
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess)
-            return HU_ERR_DEVICE;
-        const int max_blocks = max_resident_blocks(fn);
-        if (max_blocks <= 0)
-            return HU_ERR_DEVICE;
-        int cus = 0;
-        {
-            std::lock_guard<std::mutex> lk(g_info_mu);
-            cus = g_info[dev].cus;
-        }
-        const int per_cu = cus > 0 ? max_blocks / cus : 1;
-        const unsigned int gpc = (tuning && tuning->groups_per_cu) ? tuning->groups_per_cu : (unsigned int)per_cu;
-        const unsigned int grid = (unsigned int)(cus * (int)(gpc < (unsigned int)per_cu ? gpc : per_cu));
-        void *args[] = {&bd, &src, &dst, &results, &w};
-        if (hipLaunchKernel(fn, dim3(grid ? grid : 1), dim3(kBlock), args, 0, stream) != hipSuccess)
+    // upper bound on the items at this tile size (the plan may need fewer:
+    // the surplus workgroups leave at once); a launch holds at most 2^32 - 1
+    // work-items, so larger bounds take several launches in item order
+    const unsigned long long items = total_input_bytes / tile_bytes + 2ull * n_docs + 1;
+    constexpr unsigned long long kMaxGrid = 0xFFFFFFFFull / kBlock;
+    const void *fn = batch_run_kernel(U);
+    const size_t pad = lds_pad(fn, tuning ? tuning->groups_per_cu : 0);
+    for (unsigned long long base = 0; base < items; base += kMaxGrid) {
+        const unsigned long long grid = items - base < kMaxGrid ? items - base : kMaxGrid;
+        void *args[] = {&bd, &src, &dst, &results, &w, &base};
+        if (hipLaunchKernel(fn, dim3((unsigned int)grid), dim3(kBlock), args, pad, stream) != hipSuccess)
             return HU_ERR_DEVICE;
     }
     return hipGetLastError() == hipSuccess ? HU_OK : HU_ERR_DEVICE;
@@ -504,7 +517,7 @@ int hu_tune_batch(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return HU_ERR_DEVICE;
     const unsigned int subs[] = {1, 2, 4};
-    const unsigned int gpcs[] = {1, 2, 4, 0};
+    const unsigned int gpcs[] = {2, 4, 6, 0};
     const int reps = 3;
     double best_t = 1e300;
     hu_tuning bt{hu::kBatchDefaultU, 0};

@@ -330,8 +330,60 @@ def utf8_documents(n_docs: int = 100_000, median: int = 2048, sigma: float = 1.5
     return DocBatch(np.concatenate(parts) if parts else np.zeros(0, np.uint8), offsets, prof, inj)
 
 
-def utf16_documents(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 * MIB,
-                    error_frac: float = 0.005, pool_bytes: int | None = None, seed_key="cfg4") -> DocBatch:
+@dataclass
+class DocSpec16:
+    """UTF-16LE documents described by reference: each is a slice of one
+    profile's pool with at most two words replaced (the injected error), so a
+    multi-GiB batch can be assembled on the device from the pools without a
+    host copy of the whole batch."""
+    pools: list             # per profile (BATCH_PROFILES order): Text with u16
+    profiles: np.ndarray    # profile index per document
+    start: np.ndarray       # int64 word offset of the slice in its pool
+    length: np.ndarray      # int64 words
+    inj_pos: np.ndarray     # int64 word index of the injected error in the document, -1 if none
+    inj_words: np.ndarray   # uint16 (n, 2): words at inj_pos, inj_pos + 1 after injection
+
+    @property
+    def injected(self) -> np.ndarray:
+        return self.inj_pos >= 0
+
+    @property
+    def offsets(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.length)]).astype(np.int64)
+
+    def doc(self, d: int) -> np.ndarray:
+        """Words of document d (a fresh array)."""
+        t = self.pools[self.profiles[d]]
+        w = t.u16[self.start[d]:self.start[d] + self.length[d]].copy()
+        p = int(self.inj_pos[d])
+        if p >= 0:
+            w[p] = self.inj_words[d, 0]
+            if p + 1 < w.size:
+                w[p + 1] = self.inj_words[d, 1]
+        return w
+
+    def utf8_bytes(self, d: int) -> int:
+        """UTF-8 length of document d when it carries no injected error."""
+        t = self.pools[self.profiles[d]]
+        cs16 = self._starts16[self.profiles[d]]
+        i = int(np.searchsorted(cs16, self.start[d]))
+        j = int(np.searchsorted(cs16, self.start[d] + self.length[d]))
+        cs8 = self._starts8[self.profiles[d]]
+        return int(cs8[j] - cs8[i])
+
+    def __post_init__(self):
+        self._starts16 = [t.char_starts_u16 for t in self.pools]
+        self._starts8 = [t.char_starts_u8 for t in self.pools]
+
+    def materialize(self) -> DocBatch:
+        parts = [self.doc(d) for d in range(self.length.size)]
+        data = np.concatenate(parts) if parts else np.zeros(0, np.uint16)
+        return DocBatch(data, self.offsets, self.profiles, self.injected)
+
+
+def utf16_document_spec(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 * MIB,
+                        error_frac: float = 0.005, pool_bytes: int | None = None,
+                        seed_key="cfg4") -> DocSpec16:
     """Many UTF-16LE documents with byte lengths uniform in [lo, hi] (even),
     character-aligned slices of per-profile pools; a fraction carry one
     unpaired surrogate."""
@@ -342,7 +394,10 @@ def utf16_documents(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 
         pool_bytes = int(min(max(2 * hi_bytes, want_words.sum()), 128 * MIB))
     pools = [make_text(p, pool_bytes, rng_for(seed_key, "pool", p, pool_bytes)) for p in BATCH_PROFILES]
     pool_starts = [t.char_starts_u16 for t in pools]
-    parts, lens = [], np.zeros(n_docs, dtype=np.int64)
+    start = np.zeros(n_docs, dtype=np.int64)
+    length = np.zeros(n_docs, dtype=np.int64)
+    inj_pos = np.full(n_docs, -1, dtype=np.int64)
+    inj_words = np.zeros((n_docs, 2), dtype=np.uint16)
     inj = rng.random(n_docs) < error_frac
     for d in range(n_docs):
         t, cs = pools[prof[d]], pool_starts[prof[d]]
@@ -352,12 +407,16 @@ def utf16_documents(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 
         b0 = int(cs[i])
         j = int(np.searchsorted(cs, b0 + w, side="right")) - 1
         j = max(j, i)
-        doc = t.u16[b0:int(cs[j])]
-        if inj[d] and doc.size >= 4:
-            doc, _ = inject_utf16_error(doc, cs[i:j + 1] - b0, rng)
-        else:
-            inj[d] = False
-        parts.append(doc)
-        lens[d] = doc.size
-    offsets = np.concatenate([[0], np.cumsum(lens)])
-    return DocBatch(np.concatenate(parts) if parts else np.zeros(0, np.uint16), offsets, prof, inj)
+        start[d], length[d] = b0, int(cs[j]) - b0
+        if inj[d] and length[d] >= 4:
+            doc, pos = inject_utf16_error(t.u16[b0:int(cs[j])], cs[i:j + 1] - b0, rng)
+            inj_pos[d] = pos
+            inj_words[d, 0] = doc[pos]
+            inj_words[d, 1] = doc[pos + 1] if pos + 1 < doc.size else 0
+    return DocSpec16(pools, prof, start, length, inj_pos, inj_words)
+
+
+def utf16_documents(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 * MIB,
+                    error_frac: float = 0.005, pool_bytes: int | None = None, seed_key="cfg4") -> DocBatch:
+    """utf16_document_spec, materialised as one concatenated host array."""
+    return utf16_document_spec(n_docs, lo_bytes, hi_bytes, error_frac, pool_bytes, seed_key).materialize()

@@ -70,3 +70,17 @@ def test_document_batches_small():
     b16 = wl.utf16_documents(n_docs=100, hi_bytes=1 << 14, error_frac=0.2, pool_bytes=1 << 18, seed_key="d16")
     errs, counts = oracle.many_validate_utf16le(b16.data, b16.offsets)
     assert np.array_equal(errs != 0, b16.injected)
+
+
+def test_utf16_document_spec():
+    spec = wl.utf16_document_spec(n_docs=80, hi_bytes=1 << 13, error_frac=0.25, pool_bytes=1 << 17, seed_key="spec16")
+    b = spec.materialize()
+    offs = spec.offsets
+    assert np.array_equal(offs, b.offsets)
+    le, lc = oracle.many_utf8_length_from_utf16le(b.data, offs)
+    assert np.array_equal(le != 0, spec.injected)
+    for d in range(80):
+        assert np.array_equal(spec.doc(d), b.data[offs[d]:offs[d + 1]])
+        if not spec.injected[d]:
+            text = spec.doc(d).tobytes().decode("utf-16-le")
+            assert spec.utf8_bytes(d) == len(text.encode("utf-8")) == lc[d]

@@ -223,6 +223,89 @@ int hu_tune_batch(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
  * when there is no such entry. */
 int hu_tuning_lookup(const char *key, hu_tuning *out);
 
+/* ------------------------------------------------------------------------
+ * Server: transcoding requests from HOST memory, batched on the device as
+ * they arrive (continuous batching). A scheduler thread admits requests in
+ * arrival order while batch slots, the in-flight request limit and the device
+ * pool allow (a request waits at the head of the queue until memory is free;
+ * none is overtaken, so none starves), stages each batch in pinned host memory
+ * (one host-to-device copy of the document table and inputs), runs it with
+ * hu_batch_run, brings outputs and results back in one device-to-host copy and
+ * copies each output to the request's dst. Up to `slots` batches are in
+ * flight on their own streams, so new arrivals are batched and copied while
+ * earlier batches run. Unlike the rest of this interface, request src and dst
+ * are HOST pointers; they must stay valid until the request completes.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    uint64_t pool_bytes;      /* device memory for batch regions (0 = 8 GiB) */
+    uint64_t batch_bytes;     /* largest batch region: document table, inputs,
+                                 worst-case outputs, results; also the pinned
+                                 staging per slot (0 = 256 MiB) */
+    uint32_t batch_requests;  /* most requests per batch (0 = 4096) */
+    uint32_t max_in_flight;   /* most requests admitted and not completed (0 = 65536) */
+    uint32_t slots;           /* batches in flight, one stream each (0 = 3) */
+    uint32_t plain;           /* 1: comparison path: one request at a time, each
+                                 through the single-buffer async call (one slot,
+                                 one request per step) */
+    hu_tuning tuning;         /* launch shape of the batch kernels (zeros = defaults) */
+} hu_server_config;
+
+/* One request (48 bytes). Output capacity dst_cap is in output code units;
+ * dst may be NULL (the result alone is returned). On success exactly
+ * result.count units are written to dst; on an error nothing is. */
+typedef struct {
+    uint64_t tag;             /* returned in the completion */
+    uint32_t op;              /* HU_OP_* */
+    uint32_t reserved;        /* 0 */
+    const void *src;          /* host input: n_units code units */
+    uint64_t n_units;
+    void *dst;                /* host output or NULL */
+    uint64_t dst_cap;
+} hu_request;
+
+typedef struct {
+    uint64_t tag;
+    hu_result result;         /* as from the single-buffer call of the same op;
+                                 HU_ERR_INVALID_ARGUMENT for a request that can
+                                 never run (unknown op, larger than a batch) */
+    int64_t latency_ns;       /* arrival to output in dst, host monotonic clock */
+} hu_completion;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, batches;
+    uint64_t input_bytes, output_bytes;   /* of requests completed without error */
+    int64_t p50_ns, p99_ns, max_ns;       /* latency percentiles (nearest rank) */
+    int64_t device_ns;                    /* summed device time of the batch steps */
+    double mean_batch;                    /* requests per batch */
+} hu_server_stats;
+
+/* Creates a server on the current HIP device (cfg may be NULL: defaults).
+ * Returns HU_OK and *server, HU_ERR_INVALID_ARGUMENT or HU_ERR_DEVICE (not
+ * enough device or pinned memory). */
+int hu_server_create(const hu_server_config *cfg, void **server);
+
+/* Queues a request; its arrival time is now. Thread-safe. */
+int hu_server_submit(void *server, const hu_request *req);
+
+/* Moves up to `max` completions into out (*n_out of them), waiting up to
+ * timeout_ns for the first. Thread-safe. */
+int hu_server_poll(void *server, hu_completion *out, uint32_t max, uint32_t *n_out, int64_t timeout_ns);
+
+/* Open-loop replay: submits reqs[i] at arrival_ns[i] nanoseconds after the
+ * call starts (non-decreasing), latency counted from that scheduled time, and
+ * returns when all n have completed; out[i] receives request i's completion.
+ * Completions of a replay are not queued for hu_server_poll. */
+int hu_server_replay(void *server, const hu_request *reqs, const int64_t *arrival_ns, uint64_t n,
+                     hu_completion *out);
+
+/* Statistics since creation or the last reset. */
+int hu_server_stats_get(void *server, hu_server_stats *out);
+int hu_server_stats_reset(void *server);
+
+/* Finishes every queued and running request, then frees the server. */
+void hu_server_destroy(void *server);
+
 /* Library-wide: a human-readable name for an error code (static string). */
 const char *hu_error_name(int error);
 

@@ -93,9 +93,26 @@ lib.hu_error_name.restype = ctypes.c_char_p
 lib.hu_shutdown.argtypes = []
 lib.hu_shutdown.restype = None
 
+lib.hu_server_create.argtypes = [_p, ctypes.POINTER(_p)]
+lib.hu_server_create.restype = _i
+lib.hu_server_submit.argtypes = [_p, _p]
+lib.hu_server_submit.restype = _i
+lib.hu_server_poll.argtypes = [_p, _p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int64]
+lib.hu_server_poll.restype = _i
+lib.hu_server_replay.argtypes = [_p, _p, _p, ctypes.c_uint64, _p]
+lib.hu_server_replay.restype = _i
+lib.hu_server_stats_get.argtypes = [_p, _p]
+lib.hu_server_stats_get.restype = _i
+lib.hu_server_stats_reset.argtypes = [_p]
+lib.hu_server_stats_reset.restype = _i
+lib.hu_server_destroy.argtypes = [_p]
+lib.hu_server_destroy.restype = None
+
 EXPORTED_BATCH = ["hu_batch_workspace_bytes", "hu_batch_run", "hu_batch_graph_create", "hu_graph_launch",
                   "hu_graph_destroy", "hu_tune_batch", "hu_tuning_lookup"]
-EXPORTED = EXPORTED_BATCH + [
+EXPORTED_SERVER = ["hu_server_create", "hu_server_submit", "hu_server_poll", "hu_server_replay",
+                   "hu_server_stats_get", "hu_server_stats_reset", "hu_server_destroy"]
+EXPORTED = EXPORTED_BATCH + EXPORTED_SERVER + [
     "validate_utf8", "utf16_length_from_utf8", "convert_utf8_to_utf16le",
     "validate_utf16le", "utf8_length_from_utf16le", "convert_utf16le_to_utf8",
     "validate_utf8_async", "utf16_length_from_utf8_async", "convert_utf8_to_utf16le_async",
@@ -300,3 +317,110 @@ def tuning_lookup(key: str):
     t = HuTuning()
     rc = lib.hu_tuning_lookup(key.encode(), ctypes.byref(t))
     return t if rc == OK else None
+
+
+# ---------------------------------------------------------------- server
+
+class HuServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_uint64), ("batch_bytes", ctypes.c_uint64),
+                ("batch_requests", ctypes.c_uint32), ("max_in_flight", ctypes.c_uint32),
+                ("slots", ctypes.c_uint32), ("plain", ctypes.c_uint32), ("tuning", HuTuning)]
+
+
+class HuServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64), ("output_bytes", ctypes.c_uint64),
+                ("p50_ns", ctypes.c_int64), ("p99_ns", ctypes.c_int64), ("max_ns", ctypes.c_int64),
+                ("device_ns", ctypes.c_int64), ("mean_batch", ctypes.c_double)]
+
+
+def _np_dtypes():
+    import numpy as np
+    req = np.dtype([("tag", "<u8"), ("op", "<u4"), ("reserved", "<u4"), ("src", "<u8"), ("n_units", "<u8"),
+                    ("dst", "<u8"), ("dst_cap", "<u8")])
+    comp = np.dtype([("tag", "<u8"), ("error", "<i4"), ("reserved", "<i4"), ("count", "<u8"),
+                     ("latency_ns", "<i8")])
+    assert req.itemsize == 48 and comp.itemsize == 32
+    return req, comp
+
+
+REQUEST_DTYPE, COMPLETION_DTYPE = _np_dtypes()
+
+
+class Server:
+    """hu_server_*: requests from host (numpy) buffers, batched on the device.
+
+    Buffers handed to submit/replay must stay alive until their requests have
+    completed (the caller keeps references)."""
+
+    def __init__(self, pool_bytes=0, batch_bytes=0, batch_requests=0, max_in_flight=0, slots=0, plain=False,
+                 tuning: HuTuning | None = None):
+        cfg = HuServerConfig(pool_bytes, batch_bytes, batch_requests, max_in_flight, slots, 1 if plain else 0,
+                             tuning if tuning is not None else HuTuning(0, 0))
+        h = ctypes.c_void_p()
+        rc = lib.hu_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != OK:
+            raise RuntimeError(f"hu_server_create failed: {error_name(rc)}")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib.hu_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()
+
+    @staticmethod
+    def request(tag, op, src, dst=None, dst_cap=None):
+        """One REQUEST_DTYPE record for numpy buffers src (and dst)."""
+        import numpy as np
+        r = np.zeros(1, dtype=REQUEST_DTYPE)[0]
+        r["tag"], r["op"] = tag, op
+        r["src"] = src.ctypes.data if src.size else 0
+        r["n_units"] = src.size
+        if dst is not None:
+            r["dst"] = dst.ctypes.data
+            r["dst_cap"] = dst.size if dst_cap is None else dst_cap
+        elif dst_cap is not None:
+            r["dst_cap"] = dst_cap
+        return r
+
+    def submit(self, rec) -> int:
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(rec, dtype=REQUEST_DTYPE).reshape(1))
+        return lib.hu_server_submit(self.h, a.ctypes.data)
+
+    def poll(self, max_n=1024, timeout_s=0.0):
+        import numpy as np
+        out = np.zeros(max_n, dtype=COMPLETION_DTYPE)
+        n = ctypes.c_uint32()
+        rc = lib.hu_server_poll(self.h, out.ctypes.data, max_n, ctypes.byref(n), int(timeout_s * 1e9))
+        if rc != OK:
+            raise RuntimeError(error_name(rc))
+        return out[:n.value]
+
+    def replay(self, reqs, arrival_ns):
+        """Open-loop replay of REQUEST_DTYPE records at the given offsets (ns)."""
+        import numpy as np
+        reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+        arr = np.ascontiguousarray(arrival_ns, dtype=np.int64)
+        out = np.zeros(reqs.size, dtype=COMPLETION_DTYPE)
+        rc = lib.hu_server_replay(self.h, reqs.ctypes.data, arr.ctypes.data, reqs.size, out.ctypes.data)
+        if rc != OK:
+            raise RuntimeError(f"replay failed: {error_name(rc)}")
+        return out
+
+    def stats(self) -> dict:
+        st = HuServerStats()
+        lib.hu_server_stats_get(self.h, ctypes.byref(st))
+        return {f: getattr(st, f) for f, _ in HuServerStats._fields_}
+
+    def reset_stats(self):
+        lib.hu_server_stats_reset(self.h)

@@ -1,7 +1,8 @@
 """Build the gfx950 shared library ``libhiputf.so`` in-tree: ``python -m paper_2109_10433_amd.build``.
 
-One hipcc invocation over the single translation unit csrc/hiputf.hip. Packed
-FP32 instruction selection is disabled for all device code.
+One hipcc invocation over csrc/hiputf.hip (kernels and the C ABI) and
+csrc/serve.hip (the server, host code). Packed FP32 instruction selection is
+disabled for all device code.
 """
 from __future__ import annotations
 
@@ -24,7 +25,7 @@ HIPCC_FLAGS = [
 def build(extra=(), out: str = LIB, verbose: bool = False) -> str:
     tmp = out + ".tmp"
     cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
-           os.path.join(PKG, "csrc", "hiputf.hip"), "-o", tmp]
+           os.path.join(PKG, "csrc", "hiputf.hip"), os.path.join(PKG, "csrc", "serve.hip"), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -29,8 +29,26 @@ struct BatchDoc {                     // mirrors hu_doc
 };
 static_assert(sizeof(BatchDoc) == sizeof(hu_doc), "hu_doc layout");
 
+// Workspace of a batch call:
+//   [BatchHeader (256 B) | status, item_cap words | first_item | err | item_map]
+// The status array starts at a fixed offset; everything after it moves with
+// the call's shape (document count, item capacity). Status words must never
+// hold anything but status words or zeros, so memory that earlier calls used
+// for the per-document arrays is cleared before it becomes status words.
+struct BatchHeader {
+    unsigned long long items8;        // UTF-8 work items of this call
+    unsigned long long items16;       // UTF-16 work items
+    unsigned long long dirty_from;    // 1 + first status word that may hold other data (0: none)
+    unsigned long long clear_lo;      // status words [clear_lo, clear_hi) to clear in this call
+    unsigned long long clear_hi;
+    unsigned int epoch;               // tag of this call's status words
+    unsigned int hang;                // set if a bounded wait gave up
+    unsigned long long pad[2];
+};
+static_assert(sizeof(BatchHeader) <= kHeaderBytes, "batch header size");
+
 struct BatchWs {
-    WsHeader *hdr;                    // pad[0]: UTF-8 items, pad[1]: UTF-16 items
+    BatchHeader *hdr;
     unsigned int *first_item;         // per document
     unsigned long long *err;          // per document error key
     unsigned long long *item_map;     // per item: document index | tile index << 32
@@ -170,9 +188,14 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_plan(const BatchDoc *docs,
         }
     }
     if (threadIdx.x == 0) {
-        w.hdr->pad[0] = overflow ? 0 : t8;
-        w.hdr->pad[1] = overflow ? 0 : t16;
+        w.hdr->items8 = overflow ? 0 : t8;
+        w.hdr->items16 = overflow ? 0 : t16;
         w.hdr->hang = 0;
+        // status words of earlier calls' per-document arrays: cleared by fill
+        const unsigned long long dirty = w.hdr->dirty_from;
+        w.hdr->clear_lo = dirty ? dirty - 1 : w.item_cap;
+        w.hdr->clear_hi = w.item_cap;
+        w.hdr->dirty_from = w.item_cap + 1;
         const unsigned int e = (w.hdr->epoch + 1u) & kEpochMask;
         w.hdr->epoch = e;
         s_wrap = e == 0;
@@ -184,10 +207,17 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_plan(const BatchDoc *docs,
     }
 }
 
+// item -> (document, tile) map; every error key back to zero; status words
+// the plan marked for clearing.
 __global__ void k_batch_fill(const BatchDoc *docs, unsigned int n_docs, const uint8_t *src_base, BatchWs w,
                              unsigned long long tile_bytes)
 {
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    const unsigned long long me = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (unsigned long long i = w.hdr->clear_lo + me; i < w.hdr->clear_hi; i += stride)
+        w.status[i] = 0;
     for (unsigned int d = blockIdx.x * blockDim.x + threadIdx.x; d < n_docs; d += gridDim.x * blockDim.x) {
+        w.err[d] = 0;
         const unsigned int first = w.first_item[d];
         if (first == 0xFFFFFFFFu)
             continue;
@@ -237,7 +267,7 @@ void k_batch_run(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_bas
 {
     __shared__ BatchShared<U> s;
     const unsigned long long i = item_base + blockIdx.x;
-    const unsigned long long n8 = w.hdr->pad[0], n16 = w.hdr->pad[1];
+    const unsigned long long n8 = w.hdr->items8, n16 = w.hdr->items16;
     if (i >= n8 + n16)
         return;
     const unsigned long long m = w.item_map[i];

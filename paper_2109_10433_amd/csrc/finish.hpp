@@ -49,6 +49,11 @@ __device__ inline hu_result resolve_utf8(const uint8_t *s, unsigned long long n,
 {
     hu_result r;
     r.reserved = 0;
+    if (f >= n) {                 // flags always lie inside the input
+        r.error = HU_ERR_DEVICE;
+        r.count = 0;
+        return r;
+    }
     unsigned long long p = f >= 3 ? f - 3 : 0;
     for (int steps = 0; steps < 4 && p > 0 && (s[p] & 0xC0u) == 0x80u; ++steps)
         --p;

@@ -152,11 +152,11 @@ BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
     // the smallest tile is one 4 KiB sub-tile; each document adds at most two
     // partial tiles (alignment offset and tail)
     l.item_cap = total_input_bytes / kSub + 2ull * n_docs + 1;
-    l.first = kHeaderBytes;
+    l.status = kHeaderBytes;
+    l.first = align256(l.status + 8ull * l.item_cap);
     l.err = align256(l.first + 4ull * n_docs);
     l.map = align256(l.err + 8ull * n_docs);
-    l.status = align256(l.map + 8ull * l.item_cap);
-    l.total = align256(l.status + 8ull * l.item_cap);
+    l.total = align256(l.map + 8ull * l.item_cap);
     return l;
 }
 
@@ -203,7 +203,7 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     if (U != 1 && U != 2 && U != 4)
         return HU_ERR_INVALID_ARGUMENT;
     char *base = reinterpret_cast<char *>(ws);
-    BatchWs w{reinterpret_cast<WsHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
+    BatchWs w{reinterpret_cast<BatchHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
               reinterpret_cast<unsigned long long *>(base + l.err),
               reinterpret_cast<unsigned long long *>(base + l.map),
               reinterpret_cast<unsigned long long *>(base + l.status), l.item_cap};
@@ -214,8 +214,13 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
 
     hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanBlock), 0, stream, bd, n_docs, src, (const uint8_t *)dst,
                        results, w, tile_bytes);
-    const unsigned int fill_grid = (n_docs + 255) / 256 < 2048 ? (n_docs + 255) / 256 : 2048;
-    hipLaunchKernelGGL(k_batch_fill, dim3(fill_grid), dim3(256), 0, stream, bd, n_docs, src, w, tile_bytes);
+    // enough workgroups for the documents and for clearing the status array
+    unsigned long long fill_grid = (n_docs + 255) / 256;
+    if (fill_grid < (l.item_cap + 4095) / 4096)
+        fill_grid = (l.item_cap + 4095) / 4096;
+    fill_grid = fill_grid < 2048 ? fill_grid : 2048;
+    hipLaunchKernelGGL(k_batch_fill, dim3((unsigned int)fill_grid), dim3(256), 0, stream, bd, n_docs, src, w,
+                       tile_bytes);
     // upper bound on the items at this tile size (the plan may need fewer:
     // the surplus workgroups leave at once); a launch holds at most 2^32 - 1
     // work-items, so larger bounds take several launches in item order

@@ -284,3 +284,36 @@ def test_batch_tuner_and_cache(texts, tmp_path, monkeypatch):
     for i, (op, data, cap) in enumerate(items):
         e, c, _ = expected(op, data, cap)
         assert (int(errs[i]), int(counts[i])) == (e, c)
+
+
+def test_workspace_reused_across_batch_shapes(texts):
+    """One workspace for batches of different document counts and sizes
+    (growing and shrinking): the per-document arrays move with the shape, and
+    earlier calls' data must never be read as error keys or status words."""
+    rng = np.random.default_rng(77)
+    t8, t16 = texts
+    shapes = [(40, [100, 5000]), (3, [60000]), (300, [10, 200]), (1, [3]), (120, [9000, 30000]),
+              (500, [1, 50]), (20, [100000])]
+    max_docs = max(n for n, _ in shapes)
+    max_total = 4 << 20
+    ws = torch.zeros(hu.lib.hu_batch_workspace_bytes(max_docs, max_total) + 256, dtype=torch.uint8, device="cuda")
+    wsp, wsb = hu.workspace_ptr(ws)
+    for rep in range(2):
+        for n, sizes in shapes:
+            items = random_items(rng, n, t8, t16, sizes)
+            docs, src, dst_size = lay_out(items, rng)
+            total = int(sum(d.view(np.uint8).size for _, d, _ in items))
+            assert total <= max_total
+            src_t = torch.from_numpy(src).cuda()
+            dst_t = torch.full((dst_size,), 0xA5, dtype=torch.uint8, device="cuda")
+            docs_t = torch.from_numpy(docs.view(np.uint8).copy()).cuda()
+            res = torch.zeros((n, 16), dtype=torch.uint8, device="cuda")
+            say("shared workspace", rep, n, total)
+            rc = hu.lib.hu_batch_run(docs_t.data_ptr(), n, total, src_t.data_ptr(), dst_t.data_ptr(), res.data_ptr(),
+                                     None, wsp, wsb, hu.stream_handle())
+            assert rc == 0
+            torch.cuda.synchronize()
+            rec = res.cpu().numpy().reshape(-1).view([("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
+            for i, (op, data, cap) in enumerate(items):
+                e, c, _ = expected(op, data, cap)
+                assert (int(rec["error"][i]), int(rec["count"][i])) == (e, c), (rep, n, i, op)

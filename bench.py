@@ -19,6 +19,12 @@ documents run as one launch per document (the plain path):
     batch call, with sub-tile count and workgroups per CU from the autotuner;
   * 10 000 UTF-16LE documents (uniform 64 B - 4 MiB, mixed profiles, 0.5% with
     an unpaired surrogate) converted to UTF-8 by replaying a captured HIP graph.
+Then open-loop Poisson request traces (10k, 50k and 200k requests/s; sizes
+log-normal, median 4 KiB, 16 B - 16 MiB; 70% UTF-8 -> UTF-16LE, 30% the
+reverse; 1% invalid) are replayed from host memory through the continuous-
+batching server (8 GiB device pool) and through the plain path (one request at
+a time: copy in, one launch, copy out, wait), with p50/p99 latency from arrival
+to output in host memory.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -219,6 +225,98 @@ def bench_utf16_documents(args, hu, wl, dev, stream):
     }
 
 
+def _trace_records(hu, tr, arena):
+    """REQUEST_DTYPE records of a trace; outputs go to a host arena used as a ring."""
+    import numpy as np
+    n = tr.arrival_ns.size
+    rec = np.zeros(n, dtype=hu.REQUEST_DTYPE)
+    rec["tag"] = np.arange(n)
+    rec["op"] = tr.ops
+    rec["src"] = [x.ctypes.data for x in tr.inputs]
+    units = np.array([x.size for x in tr.inputs], dtype=np.uint64)
+    rec["n_units"] = units
+    cap = np.where(tr.ops == 2, units, 3 * units).astype(np.uint64)
+    out_bytes = np.where(tr.ops == 2, 2 * cap, cap).astype(np.uint64)
+    span = arena.nbytes - int(out_bytes.max()) - 16
+    assert span > 0
+    start = (np.concatenate([[0], np.cumsum((out_bytes + 15) // 16 * 16)[:-1]]) % span).astype(np.uint64)
+    rec["dst"] = arena.ctypes.data + start
+    rec["dst_cap"] = cap
+    return rec
+
+
+def _serve_once(hu, srv, tr, rec, n_use, label):
+    """Replays the first n_use requests of the trace; checks every result."""
+    import numpy as np
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    comps = srv.replay(rec[:n_use], tr.arrival_ns[:n_use])
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    err = comps["error"]
+    cnt = comps["count"]
+    inv = tr.invalid[:n_use]
+    want = tr.expect_count[:n_use]
+    bad = ((err != 0) != inv) | (~inv & (cnt != want))
+    if np.any(bad):
+        k = int(np.nonzero(bad)[0][0])
+        raise RuntimeError(f"{label}: request {k}: result ({err[k]}, {cnt[k]}) unexpected "
+                           f"(invalid={bool(inv[k])}, expected count {want[k]})")
+    lat = comps["latency_ns"].astype(np.float64)
+    ends = tr.arrival_ns[:n_use] + comps["latency_ns"]
+    makespan = float(ends.max() - tr.arrival_ns[0]) * 1e-9
+    moved = st["input_bytes"] + st["output_bytes"]
+    offered = n_use / max(float(tr.arrival_ns[n_use - 1] - tr.arrival_ns[0]) * 1e-9, 1e-9)
+    done_rate = n_use / makespan
+    return {
+        "requests": int(n_use),
+        "p50_ms": round(st["p50_ns"] * 1e-6, 3), "p99_ms": round(st["p99_ns"] * 1e-6, 3),
+        "mean_ms": round(float(lat.mean()) * 1e-6, 3),
+        "GBps": round(moved / makespan / 1e9, 2),
+        "completed_per_s": round(done_rate, 1),
+        "saturated": bool(done_rate < 0.95 * offered),
+        "mean_batch": round(st["mean_batch"], 1),
+        "device_busy_frac": round(st["device_ns"] * 1e-9 / makespan, 3),
+        "replay_wall_s": round(wall, 2),
+    }
+
+
+def bench_serving(args, hu, wl):
+    """Open-loop Poisson request traces through the continuous-batching server
+    and through the plain one-request-at-a-time path."""
+    import numpy as np
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    arena = np.empty(1 << 30, dtype=np.uint8)
+    arena[::4096] = 0                      # touch the pages before timing
+    out = {"pool_bytes": 8 << 30, "duration_s": args.serve_seconds, "rates": {}}
+    srv = hu.Server(pool_bytes=8 << 30, batch_bytes=256 << 20, slots=3)
+    plain = hu.Server(pool_bytes=1 << 30, batch_bytes=64 << 20, plain=True)
+    try:
+        for rate in rates:
+            t_gen = time.time()
+            tr = wl.request_trace(rate, args.serve_seconds)
+            rec = _trace_records(hu, tr, arena)
+            n = rec.size
+            log(f"serving {rate:.0f}/s: {n} requests, {sum(x.nbytes for x in tr.inputs) / 1e9:.2f} GB input, "
+                f"generated in {time.time() - t_gen:.1f}s")
+            served = _serve_once(hu, srv, tr, rec, n, f"served {rate:.0f}/s")
+            log(f"serving {rate:.0f}/s: served p50 {served['p50_ms']} ms p99 {served['p99_ms']} ms "
+                f"{served['GBps']} GB/s")
+            n_plain = min(n, args.serve_plain_max)
+            pl = _serve_once(hu, plain, tr, rec, n_plain, f"plain {rate:.0f}/s")
+            log(f"serving {rate:.0f}/s: plain p50 {pl['p50_ms']} ms p99 {pl['p99_ms']} ms {pl['GBps']} GB/s")
+            out["rates"][f"{rate:.0f}"] = {
+                "requests": int(n),
+                "offered_input_GBps": round(sum(x.nbytes for x in tr.inputs) / args.serve_seconds / 1e9, 3),
+                "served": served,
+                "plain_per_request": pl,
+            }
+    finally:
+        srv.close()
+        plain.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +330,11 @@ def main() -> int:
     ap.add_argument("--docs8", type=int, default=100_000, help="UTF-8 documents in the batched workload")
     ap.add_argument("--docs16", type=int, default=10_000, help="UTF-16LE documents in the batched workload")
     ap.add_argument("--plain-passes", type=int, default=2, help="timed passes of the per-document launches")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving traces")
+    ap.add_argument("--serve-rates", default="10000,50000,200000", help="Poisson arrival rates (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each arrival trace")
+    ap.add_argument("--serve-plain-max", type=int, default=100_000,
+                    help="requests of each trace replayed through the plain path (a prefix)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build is single-GPU (got --gpus {args.gpus}); "
@@ -404,6 +507,10 @@ def main() -> int:
         batched["utf16_documents"] = bench_utf16_documents(args, hu, wl, dev, stream)
         torch.cuda.empty_cache()
 
+    serving = None
+    if not args.no_serving:
+        serving = bench_serving(args, hu, wl)
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -441,6 +548,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "copy_ceiling_GBps": round(copy_gbs, 1),
         "batched": batched,
+        "serving": serving,
         "detail": detail,
         "kernel_sources": kernel_source_digest(),
     }

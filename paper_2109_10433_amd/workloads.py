@@ -420,3 +420,81 @@ def utf16_documents(n_docs: int = 10_000, lo_bytes: int = 64, hi_bytes: int = 4 
                     error_frac: float = 0.005, pool_bytes: int | None = None, seed_key="cfg4") -> DocBatch:
     """utf16_document_spec, materialised as one concatenated host array."""
     return utf16_document_spec(n_docs, lo_bytes, hi_bytes, error_frac, pool_bytes, seed_key).materialize()
+
+
+@dataclass
+class RequestTrace:
+    """An open-loop request trace: arrival offsets (ns), operations, and each
+    request's input as a slice of a profile pool (or its own copy when it
+    carries an injected error)."""
+    arrival_ns: np.ndarray          # int64, non-decreasing
+    ops: np.ndarray                 # uint32: 2 (UTF-8 -> UTF-16LE) or 5 (UTF-16LE -> UTF-8)
+    inputs: list                    # per request: uint8 or uint16 array
+    invalid: np.ndarray             # bool: carries an injected error
+    expect_count: np.ndarray        # uint64: output units when valid (0 for invalid ones)
+
+
+_POOL_CACHE = {}
+
+
+def _trace_pools(pool_bytes: int, seed_key):
+    """Per-profile text pools of a trace (kept for later traces of the same key)."""
+    k = (pool_bytes, seed_key)
+    if k not in _POOL_CACHE:
+        pools = [make_text(p, pool_bytes, rng_for(seed_key, "pool", p, pool_bytes)) for p in BATCH_PROFILES]
+        _POOL_CACHE.clear()
+        _POOL_CACHE[k] = (pools, [t.char_starts_u8 for t in pools], [t.char_starts_u16 for t in pools])
+    return _POOL_CACHE[k]
+
+
+def request_trace(rate_per_s: float, duration_s: float, median: int = 4096, sigma: float = 1.5,
+                  lo: int = 16, hi: int = 16 * MIB, frac_8to16: float = 0.7, invalid_frac: float = 0.01,
+                  pool_bytes: int = 32 * MIB, seed_key="cfg5") -> RequestTrace:
+    """Poisson arrivals at `rate_per_s` for `duration_s`; request sizes
+    log-normal (median 4 KiB, sigma 1.5, clipped 16 B - 16 MiB, in UTF-8 bytes
+    of the text); 70% UTF-8 -> UTF-16LE and 30% the reverse; 1% invalid. Inputs
+    are character-aligned slices of mixed-profile pools."""
+    rng = rng_for(seed_key, rate_per_s, duration_s)
+    n = max(1, int(rng.poisson(rate_per_s * duration_s)))
+    gaps = rng.exponential(1e9 / rate_per_s, size=n)
+    arrival = np.cumsum(gaps).astype(np.int64)
+    arrival -= arrival[0]
+    want = _lognormal_lengths(rng, n, median, sigma, lo, hi)
+    ops = np.where(rng.random(n) < frac_8to16, 2, 5).astype(np.uint32)
+    prof = rng.integers(0, len(BATCH_PROFILES), size=n)
+    bad = rng.random(n) < invalid_frac
+    pools, starts8, starts16 = _trace_pools(max(pool_bytes, 2 * hi), seed_key)
+    first = np.zeros(n, dtype=np.int64)          # character index range [first, last) in the pool
+    last = np.zeros(n, dtype=np.int64)
+    for p in range(len(BATCH_PROFILES)):
+        sel = np.nonzero(prof == p)[0]
+        cs8 = starts8[p]
+        total = int(cs8[-1])
+        w = np.minimum(want[sel], total)
+        upper = np.maximum(1, np.searchsorted(cs8, total - w, side="right"))
+        i = np.minimum((rng.random(sel.size) * upper).astype(np.int64), upper - 1)
+        j = np.maximum(np.searchsorted(cs8, cs8[i] + w, side="right") - 1, i)
+        first[sel], last[sel] = i, j
+    inputs, expect = [], np.zeros(n, dtype=np.uint64)
+    for k in range(n):
+        t = pools[prof[k]]
+        cs8, cs16 = starts8[prof[k]], starts16[prof[k]]
+        i, j = int(first[k]), int(last[k])
+        if ops[k] == 2:
+            doc = t.u8[int(cs8[i]):int(cs8[j])]
+            expect[k] = int(cs16[j] - cs16[i])
+            if bad[k] and doc.size >= 8:
+                kind = UTF8_ERROR_KINDS[int(rng.integers(0, len(UTF8_ERROR_KINDS)))]
+                doc, _ = inject_utf8_error(doc, cs8[i:j + 1] - cs8[i], kind, rng)
+            else:
+                bad[k] = False
+        else:
+            doc = t.u16[int(cs16[i]):int(cs16[j])]
+            expect[k] = int(cs8[j] - cs8[i])
+            if bad[k] and doc.size >= 4:
+                doc, _ = inject_utf16_error(doc, cs16[i:j + 1] - cs16[i], rng)
+            else:
+                bad[k] = False
+        inputs.append(doc)
+    expect[bad] = 0
+    return RequestTrace(arrival, ops, inputs, bad, expect)

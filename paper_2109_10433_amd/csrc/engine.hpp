@@ -319,7 +319,7 @@ __device__ __forceinline__ void emit_tile(const unsigned int *in, typename Dir::
         unsigned int lo = 0, hi = kChunk / Dir::kInUnit;
         if (!FULL)
             chunk_range<Dir>(d, tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk, lo, hi);
-        Dir::template emit<FULL>(x, lo, hi, stage, shift + excl[u], Dir::kStageUnits);
+        Dir::template emit<FULL>(x, lo, hi, stage, shift + excl[u]);
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
         copy_out<Dir>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
@@ -384,7 +384,9 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     const unsigned long long pos = s.prefix;   // output units before this tile
     if (tile == n_tiles - 1 && tid == 0)
         fin(pos + agg);
-    if (MODE == kConvert) {
+    // A tile with a flagged position makes the call fail, and the output of a
+    // failed call is unspecified: only flag-free (valid) tiles are decoded.
+    if (MODE == kConvert && tile_flag == ~0ull) {
         Out *dst = reinterpret_cast<Out *>(d.dst);
         if (tile_is_interior<U>(d, tile))
             emit_tile<Dir, U, true>(s.in, s.out, d, tile, excl, tot, pos, dst);

@@ -68,9 +68,11 @@ struct U16Dir {
         return count;
     }
 
+    // Only called for tiles without any flagged word: the output of a sub-tile
+    // then fits the staging buffer.
     template <bool FULL>
     __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
-                                                unsigned int o, unsigned int limit)
+                                                unsigned int o)
     {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -93,7 +95,7 @@ struct U16Dir {
             } else {
                 b0 = w;
             }
-            if (m != 0 && o + 3 < limit) {
+            if (m != 0) {
                 out[o] = (Out)b0;
                 if (m > 1) out[o + 1] = (Out)b1;
                 if (m > 2) out[o + 2] = (Out)b2;

@@ -224,11 +224,13 @@ struct U8Dir {
         return count;
     }
 
-    // Writes the words of the characters that start in the chunk to out[o..],
-    // dropping any that would land at or past `limit`.
+    // Writes the words of the characters that start in the chunk to out[o..].
+    // Only called for tiles without any flagged byte, so the chunk is valid
+    // UTF-8 (its last character may end in the next chunk) and the output of a
+    // sub-tile fits the staging buffer.
     template <bool FULL>
     __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
-                                                unsigned int o, unsigned int limit)
+                                                unsigned int o)
     {
         unsigned int lead[4];
         bool wide = false;   // a byte >= E0: three- or four-byte characters
@@ -237,41 +239,8 @@ struct U8Dir {
             lead[k] = not_cont(x[k + 1]) & (FULL ? 0xFFFFFFFFu : byte_range_mask(k, lo, hi));
             wide |= (ge_e0(x[k + 1]) & lead[k]) != 0;
         }
-        if (!__any(wide)) {
-            // Only one- and two-byte characters in this wave (the first case
-            // of the paper's core component, Algorithm "core component"): the
-            // word at a lead byte b with next byte n is b (b < 0x80) or
-            // ((b & 0x1F) << 6) | (n & 0x3F), computed for two positions per
-            // register in 16-bit halves; leads are placed by a masked popcount.
-            unsigned int base = o;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const unsigned int a = x[k + 1];
-                const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);   // next bytes
-                unsigned int w[2];
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
-                    const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
-                    const unsigned int n2 = __builtin_amdgcn_perm(0u, n, sel);
-                    const unsigned int two = ((a2 & 0x001F001Fu) << 6) | (n2 & 0x003F003Fu);
-                    const unsigned int hi_bit = (a2 >> 7) & 0x00010001u;      // 1 where b >= 0x80
-                    const unsigned int m = hi_bit * 0xFFFFu;
-                    w[h] = (two & m) | (a2 & ~m);
-                }
-                const unsigned int l = lead[k];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (l & (0x80u << (8 * b))) {
-                        const unsigned int r = base + __popc(l & ((1u << (8 * b)) - 1u));
-                        if (r < limit) {
-                            const unsigned int wb = w[b >> 1];
-                            out[r] = (Out)((b & 1) ? (wb >> 16) : (wb & 0xFFFFu));
-                        }
-                    }
-                }
-                base += __popc(l);
-            }
+        if (FULL && !__any(wide)) {
+            emit_narrow(x, lead, out, o);
             return;
         }
 #pragma unroll
@@ -283,12 +252,69 @@ struct U8Dir {
                 unsigned int w = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], m);
                 unsigned int u0, u1;
                 int nw = decode_utf8_char(w, &u0, &u1);
-                if (o + 1 < limit) {
-                    out[o] = (Out)u0;
-                    if (nw == 2)
-                        out[o + 1] = (Out)u1;
-                }
+                out[o] = (Out)u0;
+                if (nw == 2)
+                    out[o + 1] = (Out)u1;
                 o += nw;
+            }
+        }
+    }
+
+    // Only one- and two-byte characters in the wave (the first case of the
+    // paper's Algorithm "core component"). The word at byte position p is b
+    // (b < 0x80) or ((b & 0x1F) << 6) | (next & 0x3F) for a lead b >= 0xC0;
+    // words are formed two per register (16-bit halves) for all 16 positions,
+    // junk at continuation bytes. Every position then stores its word without
+    // a branch, positions in descending order, at the slot of the last lead at
+    // or before it: a continuation byte's junk lands in the slot of its lead,
+    // which the lead (stored later) overwrites. Only byte 0 can precede the
+    // chunk's first lead (a 2-byte character begun in the previous chunk); it
+    // stores only when it is a lead.
+    __device__ __forceinline__ static void emit_narrow(const unsigned int x[6], const unsigned int lead[4], Out *out,
+                                                       unsigned int o)
+    {
+        unsigned int W[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const unsigned int a = x[k + 1];
+            const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);   // next bytes
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
+                const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
+                const unsigned int n2 = __builtin_amdgcn_perm(0u, n, sel);
+                // bits 6..10 from the lead's low five bits, bits 0..5 from the next byte
+                const unsigned int two = (((a2 << 6) & 0x07C007C0u) | (n2 & 0x003F003Fu));
+                const unsigned int m = ((a2 >> 7) & 0x00010001u) * 0xFFFFu;   // halves with b >= 0x80
+                W[2 * k + h] = (two & m) | (a2 & ~m);
+            }
+        }
+        // first slot of each dword's characters
+        unsigned int first[4];
+        first[0] = o;
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            first[k] = first[k - 1] + __popc(lead[k - 1]);
+        char *base = reinterpret_cast<char *>(out);
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+            // byte b of incl: leads among bytes 0..b of this dword
+            const unsigned int q = lead[k] >> 7;
+            const unsigned int s1 = q + (q << 8);
+            const unsigned int incl = s1 + (s1 << 16);
+            const unsigned int a0 = 2u * first[k] - 2u;   // address of slot (first - 1)
+#pragma unroll
+            for (int b = 3; b >= 0; --b) {
+                const unsigned int addr = a0 + 2u * ((incl >> (8 * b)) & 0xFFu);
+                const unsigned int wv = W[2 * k + (b >> 1)];
+                unsigned short *p = reinterpret_cast<unsigned short *>(base + addr);
+                const unsigned short v = (unsigned short)((b & 1) ? (wv >> 16) : wv);
+                if (k == 0 && b == 0) {
+                    if (q & 1u)
+                        *p = v;
+                } else {
+                    *p = v;
+                }
             }
         }
     }

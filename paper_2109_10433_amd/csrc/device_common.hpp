@@ -73,11 +73,13 @@ constexpr unsigned int kSpinLimit = 1u << 22;
 // Decoupled look-back, executed by one whole wave64 (all 64 lanes active).
 // Returns the sum of the values of tiles [first, tile) of the chain, where
 // `first` is the chain's first tile (its predecessors belong to nobody).
-// Each round reads a window of 256 predecessors in one memory round trip:
-// lane l inspects tiles hi - 4l .. hi - 4l - 3 (newest first). The window is
-// wide because with hundreds of tiles in flight the nearest inclusive prefix is
-// typically hundreds of tiles back, and each status read goes to memory.
-constexpr int kLookWidth = 4;
+// Each round reads the 32 newest predecessors not yet accounted for, one per
+// lane (lane l: tile hi - l), in one memory round trip. Status reads bypass
+// the per-XCD caches, and every spinning round re-reads its window: measured
+// on the large-buffer convert, rounds of 32 reads beat 64, 128 and 256 (less
+// traffic on the hot status lines) and 8 (more rounds to reach an inclusive
+// prefix).
+constexpr int kLookLanes = 32;
 
 __device__ unsigned long long lookback(unsigned long long *status, long long first, long long tile,
                                        unsigned int epoch, unsigned int *hang_flag)
@@ -87,33 +89,20 @@ __device__ unsigned long long lookback(unsigned long long *status, long long fir
     long long hi = tile - 1;             // newest predecessor not yet accounted
     unsigned int spins = 0;
     while (hi >= first) {
-        unsigned int flag[kLookWidth];
-        unsigned long long val[kLookWidth];
-#pragma unroll
-        for (int j = 0; j < kLookWidth; ++j) {
-            const long long t = hi - (kLookWidth * lane + j);
-            flag[j] = kFlagInclusive;    // before the chain's start: a stop of value 0
-            val[j] = 0;
+        const long long t = hi - lane;
+        unsigned int flag = kFlagAggregate;   // lanes past the window: neutral
+        unsigned long long val = 0;
+        if (lane < kLookLanes) {
+            flag = kFlagInclusive;            // before the chain's start: a stop of value 0
             if (t >= first) {
                 const unsigned long long w = peek(&status[t]);
-                flag[j] = ((w >> kEpochShift) == epoch) ? (unsigned int)((w >> kFlagShift) & 3u) : 0u;
-                val[j] = w & kValueMask;
+                flag = ((w >> kEpochShift) == epoch) ? (unsigned int)((w >> kFlagShift) & 3u) : 0u;
+                val = w & kValueMask;
             }
         }
-        int lstop = kLookWidth;          // first inclusive entry of this lane
-        bool lpend = false;              // an unpublished entry before it
-#pragma unroll
-        for (int j = 0; j < kLookWidth; ++j) {
-            if (lstop == kLookWidth) {
-                if (flag[j] == 0)
-                    lpend = true;
-                else if (flag[j] == kFlagInclusive)
-                    lstop = j;
-            }
-        }
-        const unsigned long long stops = __ballot(lstop < kLookWidth);
+        const unsigned long long stops = __ballot(flag == kFlagInclusive);
         const int first_lane = stops ? __ffsll((long long)stops) - 1 : 64;
-        if (__ballot(lane <= first_lane && lpend)) {
+        if (__ballot(lane <= first_lane && flag == 0)) {
             if (++spins > kSpinLimit) {
                 if (lane == 0) {
                     // completes before the caller publishes anything
@@ -134,16 +123,13 @@ __device__ unsigned long long lookback(unsigned long long *status, long long fir
                 __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        unsigned long long v = 0;
-#pragma unroll
-        for (int j = 0; j < kLookWidth; ++j)
-            v += (lane < first_lane || (lane == first_lane && j <= lstop)) ? val[j] : 0ull;
-        for (int off = 32; off > 0; off >>= 1)
+        unsigned long long v = lane <= first_lane ? val : 0ull;
+        for (int off = 16; off > 0; off >>= 1)      // lanes 32..63 hold 0
             v += __shfl_xor(v, off, 64);
-        sum += v;
+        sum += v;                                   // lane 0 holds the window's sum
         if (first_lane < 64)
             break;
-        hi -= 64 * kLookWidth;
+        hi -= kLookLanes;
         spins = 0;
     }
     return sum;

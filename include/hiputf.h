@@ -75,7 +75,7 @@ enum {
 
 /* ------------------------------------------------------------------------
  * Synchronous calls. Each enqueues its kernels on `stream`, waits for that
- * stream, and returns the result. Scratch memory (a few bytes per 4 KiB of
+ * stream, and returns the result. Scratch memory (128 bytes per 16 KiB of
  * input) comes from a per-device, per-stream cache owned by the library
  * (freed by hu_shutdown). n = 0 returns {HU_OK, 0}; pointers may then be NULL.
  * A NULL src (or dst with a non-zero capacity) with n > 0 is

@@ -237,7 +237,7 @@ __device__ __forceinline__ void batch_item(ConvertShared<Dir, U> &s, const Batch
         build_pair_table(s.table);
     const Doc d = make_doc(b, src_base, dst_base);
     const unsigned long long n_tiles = doc_tiles(b, src_base, (unsigned long long)U * kSub);
-    const Chain cx{w.status, i - tile, i, epoch, &w.err[di], &w.hdr->hang};
+    const Chain cx{w.status, i - tile, i, epoch, &w.err[di], &w.hdr->hang, 1u};
     const CallInfo call{d.base + d.off_b, d.n, d.cap, (int)b.op};
     auto fin = [&](unsigned long long total) {
         const unsigned long long key = __hip_atomic_load(&w.err[di], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

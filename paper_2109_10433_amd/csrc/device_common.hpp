@@ -81,8 +81,13 @@ constexpr unsigned int kSpinLimit = 1u << 22;
 // prefix).
 constexpr int kLookLanes = 32;
 
-__device__ unsigned long long lookback(unsigned long long *status, long long first, long long tile,
-                                       unsigned int epoch, unsigned int *hang_flag)
+// Status words of the single-buffer calls sit 128 bytes apart (each on its own
+// cache line): tiles publishing from different XCDs then never write the same
+// line, and the look-back's reads of one round go to distinct lines.
+constexpr unsigned int kStatusStride = 16;
+
+__device__ unsigned long long lookback(unsigned long long *status, unsigned int stride, long long first,
+                                       long long tile, unsigned int epoch, unsigned int *hang_flag)
 {
     const int lane = threadIdx.x & 63;
     unsigned long long sum = 0;
@@ -95,7 +100,7 @@ __device__ unsigned long long lookback(unsigned long long *status, long long fir
         if (lane < kLookLanes) {
             flag = kFlagInclusive;            // before the chain's start: a stop of value 0
             if (t >= first) {
-                const unsigned long long w = peek(&status[t]);
+                const unsigned long long w = peek(&status[(unsigned long long)t * stride]);
                 flag = ((w >> kEpochShift) == epoch) ? (unsigned int)((w >> kFlagShift) & 3u) : 0u;
                 val = w & kValueMask;
             }
@@ -120,7 +125,7 @@ __device__ unsigned long long lookback(unsigned long long *status, long long fir
                 __hip_atomic_load(hang_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
                 return 0;
             if (spins > 8)
-                __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_s_sleep(4);
             continue;
         }
         unsigned long long v = lane <= first_lane ? val : 0ull;

@@ -331,12 +331,13 @@ __device__ __forceinline__ void emit_tile(const unsigned int *in, typename Dir::
 // ------------------------------------------------------------ chained tiles
 // Where a tile sits in a look-back chain: one chain per document.
 struct Chain {
-    unsigned long long *status;      // status words, indexed by item
+    unsigned long long *status;      // status words: item i at status[i * stride]
     unsigned long long first;        // item index of the document's first tile
     unsigned long long item;         // item index of this tile
     unsigned int epoch;
     unsigned long long *err_key;     // the document's error key
     unsigned int *hang;
+    unsigned int stride;
 };
 
 // One tile of a document in a look-back chain: load, validate, count, scan,
@@ -368,15 +369,15 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     if (tid == 0) {
         if (tile_flag != ~0ull)
             report_flag(cx.err_key, tile_flag);
-        publish(&cx.status[cx.item], pack_status(cx.epoch, first ? kFlagInclusive : kFlagAggregate, agg));
+        publish(&cx.status[cx.item * cx.stride], pack_status(cx.epoch, first ? kFlagInclusive : kFlagAggregate, agg));
     }
     if (tid < 64) {
         unsigned long long excl_tile = 0;
         if (!first)
-            excl_tile = lookback(cx.status, (long long)cx.first, (long long)cx.item, cx.epoch, cx.hang);
+            excl_tile = lookback(cx.status, cx.stride, (long long)cx.first, (long long)cx.item, cx.epoch, cx.hang);
         if (tid == 0) {
             if (!first)
-                publish(&cx.status[cx.item], pack_status(cx.epoch, kFlagInclusive, excl_tile + agg));
+                publish(&cx.status[cx.item * cx.stride], pack_status(cx.epoch, kFlagInclusive, excl_tile + agg));
             s.prefix = excl_tile;
         }
     }
@@ -421,7 +422,7 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
     if (Dir::kNeedsTable)
         build_pair_table(s.table);
     const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang};
+    const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang, kStatusStride};
     unsigned long long *s_wrap = &s.red[0];
     chained_tile<Dir, U, kConvert>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
         finish_call(call, hdr, total, status, status_cap, out, s_wrap);

@@ -106,7 +106,7 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     if (op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u))
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned long long n_tiles = n ? tiles_for(op, src, n) : 0;
-    if (ws_bytes < kHeaderBytes + 8 * n_tiles)
+    if (ws_bytes < kHeaderBytes + 8ull * kStatusStride * n_tiles)
         return HU_ERR_INVALID_ARGUMENT;
 
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
@@ -320,7 +320,7 @@ hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, uns
     if (slot == nullptr)
         return make_result(HU_ERR_DEVICE, 0);
     std::lock_guard<std::mutex> lk(slot->mu);
-    const size_t need = kHeaderBytes + 8 * tiles_for(op, src, n);
+    const size_t need = kHeaderBytes + 8ull * kStatusStride * tiles_for(op, src, n);
     if (slot->d_result == nullptr) {
         if (hipMalloc((void **)&slot->d_result, 256) != hipSuccess ||
             hipHostMalloc((void **)&slot->h_result, sizeof(hu_result), hipHostMallocDefault) != hipSuccess) {
@@ -400,7 +400,7 @@ size_t hu_workspace_bytes(int op, size_t n_units)
     // worst case over source alignments: 15 bytes of offset
     const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
     const unsigned long long tb = hu::choose_kernel(op).tile_bytes;
-    return hu::kHeaderBytes + 8 * ((bytes + 15 + tb - 1) / tb);
+    return hu::kHeaderBytes + 8ull * hu::kStatusStride * ((bytes + 15 + tb - 1) / tb);
 }
 
 int hu_workspace_init(void *ws, size_t ws_bytes, void *stream)

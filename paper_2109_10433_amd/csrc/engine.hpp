@@ -132,6 +132,21 @@ __device__ __forceinline__ bool tile_is_interior(const Doc &d, unsigned long lon
     return tv >= d.off_b && tv + (unsigned long long)U * kSub < d.end_b;
 }
 
+// Truncation at the input's end, for the chunk at byte position cv (edge
+// tiles): lowers flag_min to the lead of a last character cut short.
+template <class Dir>
+__device__ __forceinline__ void end_check(const unsigned int x[6], const Doc &d, unsigned long long cv,
+                                          unsigned long long &flag_min)
+{
+    if (cv < d.end_b && cv + kChunk >= d.end_b) {
+        const int j = Dir::end_truncation(x, (int)(d.end_b - cv));
+        if (j != kNoFlag) {
+            const unsigned long long pos = (cv - d.off_b) + (long long)j * Dir::kInUnit;
+            flag_min = pos < flag_min ? pos : flag_min;
+        }
+    }
+}
+
 // Validation and counting of a staged tile. Returns the per-chunk counts in
 // c[] and lowers flag_min to the first flagged input byte position.
 template <class Dir, int U, bool COUNT, bool FULL>
@@ -166,10 +181,74 @@ template <class Dir, int U, bool COUNT>
 __device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
                                              unsigned long long tile, unsigned int c[U], unsigned long long &flag_min)
 {
-    if (tile_is_interior<U>(d, tile))
-        analyze_tile_as<Dir, U, COUNT, true>(in, table, d, tile, c, flag_min);
-    else
-        analyze_tile_as<Dir, U, COUNT, false>(in, table, d, tile, c, flag_min);
+    analyze_tile_as<Dir, U, COUNT, true>(in, table, d, tile, c, flag_min);
+    if (!tile_is_interior<U>(d, tile)) {
+        // Tiles at the input's edges hold zeros outside the input: each zero
+        // counts as one unit (an ASCII byte or word), and the only flags they
+        // raise are those of a last character cut short by the end, at a
+        // position past it; that truncation is reported at the last unit
+        // (the first-error decode in finish.hpp starts up to three bytes
+        // before the flag and finds it).
+        const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+#pragma unroll 1
+        for (int u = 0; u < U; ++u) {
+            const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
+            if (COUNT) {
+                unsigned int lo, hi;
+                chunk_range<Dir>(d, cv, lo, hi);
+                c[u] -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
+            }
+            unsigned int x[6];
+            read_chunk(in, u, x);
+            end_check<Dir>(x, d, cv, flag_min);
+        }
+        const unsigned long long n_b = d.end_b - d.off_b;
+        if (flag_min != ~0ull && flag_min >= n_b)
+            flag_min = n_b - Dir::kInUnit;
+    }
+}
+
+// Validation (and counting) of a staged tile for the validate / length
+// kernels: one sub-tile at a time in a rolled loop (the convert kernel keeps
+// the per-sub-tile counts and unrolls; here only their sum matters, and a
+// rolled loop keeps one sub-tile's values live at a time). Edge tiles: as in
+// analyze_tile.
+template <class Dir, int U, bool COUNT>
+__device__ __forceinline__ void scan_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
+                                          unsigned long long tile, unsigned long long &total,
+                                          unsigned long long &flag_min)
+{
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    const bool interior = tile_is_interior<U>(d, tile);
+    unsigned int sum = 0;
+#pragma unroll 1
+    for (int u = 0; u < U; ++u) {
+        unsigned int x[6];
+        read_chunk(in, u, x);
+        const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
+        int f;
+        unsigned int c = Dir::template analyze<COUNT, true>(x, 0u, kChunk / Dir::kInUnit, -1, table, &f);
+        if (f != kNoFlag) {
+            const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
+            flag_min = pos < flag_min ? pos : flag_min;
+        }
+        if (!interior) {
+            if (COUNT) {
+                unsigned int lo, hi;
+                chunk_range<Dir>(d, cv, lo, hi);
+                c -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
+            }
+            end_check<Dir>(x, d, cv, flag_min);
+        }
+        sum += c;
+    }
+    if (COUNT)
+        total += sum;
+    if (!interior) {
+        const unsigned long long n_b = d.end_b - d.off_b;
+        if (flag_min != ~0ull && flag_min >= n_b)
+            flag_min = n_b - Dir::kInUnit;
+    }
 }
 
 // Exclusive offsets of every thread's count for each of U sub-tiles, and the
@@ -284,13 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
         const unsigned long long next = tile + gridDim.x;
         if (next < n_tiles)
             load_tile<U>(d, next, q, pre, post);      // in flight during this tile's work
-        unsigned int c[U];
-        analyze_tile<Dir, U, MODE == kLength>(s.in, s.table, d, tile, c, my_flag);
-        if (MODE == kLength) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                my_total += c[u];
-        }
+        scan_tile<Dir, U, MODE == kLength>(s.in, s.table, d, tile, my_total, my_flag);
         __syncthreads();
         tile = next;
     }

@@ -59,7 +59,7 @@ constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 
 
 // sub-tiles per tile (tile = U x 4 KiB of input)
 constexpr int kUConvert = 4;
-constexpr int kUScan = 4;
+constexpr int kUScan = 8;
 
 struct KernelChoice {
     const void *fn;

@@ -68,6 +68,13 @@ struct U16Dir {
         return count;
     }
 
+    // A high surrogate in the last word is flagged by analyze itself (its
+    // successor reads as zero): nothing to add at the end of the input.
+    __device__ __forceinline__ static int end_truncation(const unsigned int * /*x*/, int /*end_pos*/)
+    {
+        return kNoFlag;
+    }
+
     // Only called for tiles without any flagged word: the output of a sub-tile
     // then fits the staging buffer.
     template <bool FULL>

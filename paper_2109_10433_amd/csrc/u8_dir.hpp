@@ -224,6 +224,25 @@ struct U8Dir {
         return count;
     }
 
+    // A lead byte among the last three input bytes that needs more bytes than
+    // remain: its position (relative to the chunk start; the input ends at
+    // end_pos in (0, 16]), else kNoFlag. Bytes before the chunk come from x[0];
+    // bytes outside the input read as zero and never match.
+    __device__ __forceinline__ static int end_truncation(const unsigned int x[6], int end_pos)
+    {
+#pragma unroll
+        for (int back = 3; back >= 1; --back) {
+            const int j = end_pos - back;   // >= -2
+            const int i = j + 4;            // index into the 24 bytes of x[0..5]
+            const unsigned int dw = i < 4 ? x[0] : i < 8 ? x[1] : i < 12 ? x[2] : i < 16 ? x[3] : x[4];
+            const unsigned int b = (dw >> (8 * (i & 3))) & 0xFFu;
+            const unsigned int need = b >= 0xF0u ? 4u : b >= 0xE0u ? 3u : b >= 0xC0u ? 2u : 1u;
+            if (need > (unsigned int)back)
+                return j;
+        }
+        return kNoFlag;
+    }
+
     // Writes the words of the characters that start in the chunk to out[o..].
     // Only called for tiles without any flagged byte, so the chunk is valid
     // UTF-8 (its last character may end in the next chunk) and the output of a

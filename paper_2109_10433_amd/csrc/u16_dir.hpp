@@ -81,6 +81,14 @@ struct U16Dir {
     __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
                                                 unsigned int o)
     {
+        if (FULL) {
+            // words of three UTF-8 bytes or surrogates anywhere in the wave?
+            const bool wide = ((x[1] | x[2] | x[3] | x[4]) & 0xF800F800u) != 0;
+            if (!__any(wide)) {
+                emit_narrow(x, out, o);
+                return;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j), nw = word(x, j + 1);
@@ -109,6 +117,28 @@ struct U16Dir {
                 if (m > 3) out[o + 3] = (Out)b3;
             }
             o += m;
+        }
+    }
+
+    // Only words below U+0800 in the wave (the paper's section 5 cases of one
+    // and two output bytes): byte 0 is w (w < 0x80) or 0xC0 | w >> 6, byte 1 is
+    // 0x80 | (w & 0x3F). Both are stored for every word, words in ascending
+    // order, at the word's output offset: a one-byte word's second byte lands
+    // on the next word's first byte, which the next word overwrites. The
+    // chunk's last word stores its second byte only when it has one (it must
+    // not spill into the next thread's output).
+    __device__ __forceinline__ static void emit_narrow(const unsigned int x[6], Out *out, unsigned int o)
+    {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const unsigned int w = word(x, j);
+            const bool two = w >= 0x80u;
+            const unsigned int b0 = two ? (0xC0u | (w >> 6)) : w;
+            const unsigned int b1 = 0x80u | (w & 0x3Fu);
+            out[o] = (Out)b0;
+            if (j < 7 || two)
+                out[o + 1] = (Out)b1;
+            o += two ? 2u : 1u;
         }
     }
 };

@@ -25,6 +25,9 @@ reverse; 1% invalid) are replayed from host memory through the continuous-
 batching server (8 GiB device pool) and through the plain path (one request at
 a time: copy in, one launch, copy out, wait), with p50/p99 latency from arrival
 to output in host memory.
+Last, an input-size sweep (1 B - 256 MiB of the mixed profile, both
+directions) times single calls back to back and one synchronous call at a
+time, with the CPU oracle on the same inputs up to 16 MiB.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -107,6 +110,13 @@ def bench_utf8_documents(args, hu, wl, dev, stream):
     log(f"utf8 documents: tuned sub_tiles={best.sub_tiles} groups_per_cu={best.groups_per_cu} ({best_us:.0f} us)")
 
     t_batch = _time_on_stream(lambda: batch.run(best, stream), stream, args.steps)
+    g = batch.graph(best)
+    try:
+        hu.graph_launch(g, stream)
+        t_graph = _time_on_stream(lambda: hu.graph_launch(g, stream), stream, args.steps)
+    finally:
+        torch.cuda.synchronize()
+        hu.graph_destroy(g)
     errs, counts = batch.results_host()
     bad = errs != 0
     if not np.array_equal(bad, b.injected):
@@ -128,6 +138,15 @@ def bench_utf8_documents(args, hu, wl, dev, stream):
     h = recs.cpu().numpy().reshape(-1).view([("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
     if not (np.array_equal(h["error"], errs) and np.array_equal(h["count"], counts)):
         raise RuntimeError("utf8 documents: batched and per-document results differ")
+    # naive use: one synchronous call per document, on a prefix of the batch
+    n_sync = min(n, args.sync_docs)
+    fs = hu.lib.convert_utf8_to_utf16le
+    t0 = time.perf_counter()
+    for i in range(n_sync):
+        r = fs(sp + offs[i], ls[i], dp + 2 * offs[i], ls[i], sh)
+        if (r.error, r.count) != (int(errs[i]), int(counts[i])):
+            raise RuntimeError(f"utf8 documents: synchronous call {i} disagrees with the batch")
+    t_sync = (time.perf_counter() - t0) / n_sync * n
     algo = total + out_bytes
     return {
         "workload": f"{n} UTF-8 documents -> UTF-16LE, log-normal lengths (median 2 KiB, 16 B-1 MiB), "
@@ -136,9 +155,14 @@ def bench_utf8_documents(args, hu, wl, dev, stream):
         "tuning": {"sub_tiles": best.sub_tiles, "groups_per_cu": best.groups_per_cu, "tile_bytes": 4096 * best.sub_tiles},
         "batched": {"ms": round(t_batch * 1e3, 3), "docs_per_s": round(n / t_batch, 1),
                     "GBps": round(algo / t_batch / 1e9, 1)},
+        "batched_graph": {"ms": round(t_graph * 1e3, 3), "docs_per_s": round(n / t_graph, 1),
+                          "GBps": round(algo / t_graph / 1e9, 1)},
         "plain_per_document_launches": {"ms": round(t_plain * 1e3, 3), "docs_per_s": round(n / t_plain, 1),
                                         "GBps": round(algo / t_plain / 1e9, 2)},
+        "plain_per_document_sync_calls": {"docs_timed": n_sync, "ms_for_all_docs": round(t_sync * 1e3, 1),
+                                          "docs_per_s": round(n / t_sync, 1)},
         "speedup_batched_vs_plain": round(t_plain / t_batch, 1),
+        "speedup_batched_vs_sync_calls": round(t_sync / t_batch, 1),
     }
 
 
@@ -281,6 +305,68 @@ def _serve_once(hu, srv, tr, rec, n_use, label):
     }
 
 
+SWEEP_SIZES = (1, 16, 256, 4096, 65536, 1 << 20, 16 << 20, 256 << 20)
+
+
+def _prefix8(text, n):
+    """The longest character-aligned UTF-8 prefix of at most n bytes (at least
+    one character) and its UTF-16LE words."""
+    import numpy as np
+    if not hasattr(text, "_starts"):
+        text._starts = (text.char_starts_u8, text.char_starts_u16)
+    cs8, cs16 = text._starts
+    k = max(int(np.searchsorted(cs8, n, side="right")) - 1, 1)   # at least one character
+    return text.u8[:int(cs8[k])], text.u16[:int(cs16[k])]
+
+
+def bench_size_sweep(args, hu, wl, dev, stream, text):
+    """Single-buffer calls from 1 B to 256 MiB of the mixed profile, both
+    directions: per-call time back to back (async, HIP events) and one
+    synchronous call at a time (host clock)."""
+    import torch
+    out = {}
+    sh = hu.stream_handle(stream)
+    # the UTF-16 side of the largest prefix has the most tiles (2 bytes per word)
+    ws = hu.workspace(hu.OP_CONVERT_UTF16LE_TO_UTF8, max(SWEEP_SIZES), dev)
+    wsp, wsb = hu.workspace_ptr(ws)
+    rec = torch.zeros(16, dtype=torch.uint8, device=dev)
+    for size in SWEEP_SIZES:
+        u8, u16 = _prefix8(text, size)
+        s8 = torch.from_numpy(u8.copy()).to(dev)
+        s16 = torch.from_numpy(u16.view("<i2").copy()).to(dev)
+        d16 = torch.empty(max(u8.size, 1), dtype=torch.int16, device=dev)
+        d8 = torch.empty(max(3 * u16.size, 1), dtype=torch.uint8, device=dev)
+        reps = max(5, min(1000, int(2e8 // max(u8.size, 1))))
+        entry = {"utf8_bytes": int(u8.size), "utf16_words": int(u16.size)}
+        for name, call, scall, moved in (
+            ("u8u16", lambda: hu.lib.convert_utf8_to_utf16le_async(s8.data_ptr(), u8.size, d16.data_ptr(), u8.size,
+                                                                   rec.data_ptr(), wsp, wsb, sh),
+             lambda: hu.lib.convert_utf8_to_utf16le(s8.data_ptr(), u8.size, d16.data_ptr(), u8.size, sh),
+             u8.size + 2 * u16.size),
+            ("u16u8", lambda: hu.lib.convert_utf16le_to_utf8_async(s16.data_ptr(), u16.size, d8.data_ptr(),
+                                                                   3 * u16.size, rec.data_ptr(), wsp, wsb, sh),
+             lambda: hu.lib.convert_utf16le_to_utf8(s16.data_ptr(), u16.size, d8.data_ptr(), 3 * u16.size, sh),
+             2 * u16.size + u8.size)):
+            rc = call()
+            if rc != 0:
+                raise RuntimeError(f"size sweep {size} {name}: enqueue failed with {hu.error_name(rc)}")
+            t_async = _time_on_stream(call, stream, reps)
+            srep = max(3, min(200, reps))
+            scall()
+            t0 = time.perf_counter()
+            for _ in range(srep):
+                r = scall()
+            t_sync = (time.perf_counter() - t0) / srep
+            if r.error != 0:
+                raise RuntimeError(f"size sweep {size} {name}: error {r.error}")
+            entry[name] = {"async_us": round(t_async * 1e6, 2), "sync_us": round(t_sync * 1e6, 2),
+                           "GBps_async": round(moved / t_async / 1e9, 2)}
+        out[str(size)] = entry
+        log(f"size sweep {size} B: " + ", ".join(f"{k} {v['async_us']} us" for k, v in entry.items()
+                                                  if isinstance(v, dict)))
+    return out
+
+
 def bench_serving(args, hu, wl):
     """Open-loop Poisson request traces through the continuous-batching server
     and through the plain one-request-at-a-time path."""
@@ -331,6 +417,9 @@ def main() -> int:
     ap.add_argument("--docs16", type=int, default=10_000, help="UTF-16LE documents in the batched workload")
     ap.add_argument("--plain-passes", type=int, default=2, help="timed passes of the per-document launches")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving traces")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the input-size sweep")
+    ap.add_argument("--sync-docs", type=int, default=10_000,
+                    help="documents of the UTF-8 batch also run as synchronous calls (a prefix)")
     ap.add_argument("--serve-rates", default="10000,50000,200000", help="Poisson arrival rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each arrival trace")
     ap.add_argument("--serve-plain-max", type=int, default=100_000,
@@ -511,6 +600,11 @@ def main() -> int:
     if not args.no_serving:
         serving = bench_serving(args, hu, wl)
 
+    sweep, sweep_text = None, None
+    if not args.no_sweep:
+        sweep_text = wl.make_text("mix", max(SWEEP_SIZES), wl.rng_for("size-sweep"))
+        sweep = bench_size_sweep(args, hu, wl, dev, stream, sweep_text)
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -523,6 +617,17 @@ def main() -> int:
             cpu_t += time.perf_counter() - t1
             assert r.error == 0 and r.count == t.u16.size
             cpu_bytes += t.u8.size + 2 * t.u16.size
+        if sweep is not None:
+            # the oracle on the same prefixes (up to 16 MiB): where the host catches up
+            for size in SWEEP_SIZES:
+                if size > (16 << 20):
+                    continue
+                u8, u16 = _prefix8(sweep_text, size)
+                reps = max(3, min(1000, int(2e7 // max(u8.size, 1))))
+                t1 = time.perf_counter()
+                for _ in range(reps):
+                    oracle.convert_utf8_to_utf16le(u8)
+                sweep[str(size)]["u8u16"]["cpu_oracle_us"] = round((time.perf_counter() - t1) / reps * 1e6, 2)
         cpu = {"value": round(cpu_bytes / cpu_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"validating UTF-8->UTF-16LE of the same {len(profiles)} x {args.size_mib} MiB profiles, "
                          f"one pass each, single thread ({cpu_t:.1f} s)"}
@@ -549,6 +654,7 @@ def main() -> int:
         "copy_ceiling_GBps": round(copy_gbs, 1),
         "batched": batched,
         "serving": serving,
+        "size_sweep": sweep,
         "detail": detail,
         "kernel_sources": kernel_source_digest(),
     }

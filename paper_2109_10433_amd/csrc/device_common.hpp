@@ -140,6 +140,19 @@ __device__ unsigned long long lookback(unsigned long long *status, unsigned int 
     return sum;
 }
 
+// ---------------------------------------------------------------- lanes
+// Lane l receives lane l - 1's value (DPP wave shift; lane 0 receives 0).
+__device__ __forceinline__ unsigned int from_lower_lane(unsigned int v)
+{
+    return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, true);
+}
+
+// Lane l receives lane l + 1's value (lane 63 receives 0).
+__device__ __forceinline__ unsigned int from_upper_lane(unsigned int v)
+{
+    return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, true);
+}
+
 // ---------------------------------------------------------------- scans
 __device__ __forceinline__ unsigned int wave_inclusive_sum(unsigned int v)
 {

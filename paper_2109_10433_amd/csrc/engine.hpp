@@ -1,20 +1,24 @@
 // engine.hpp - tile engine shared by both transcoding directions (gfx950).
 //
 // An input is cut into tiles of U sub-tiles of 4 KiB. A workgroup of 256
-// threads loads a whole tile with U coalesced 16-byte loads per thread (the
-// next tile's loads are issued before the current tile's work, so they are in
-// flight meanwhile) and stages it in LDS with the 16 bytes on either side, so
-// every thread sees the 4 bytes before and after its 16-byte chunk. The
+// threads loads a whole tile with U coalesced 16-byte loads per thread, and
+// every thread also needs the 4 bytes before and after its 16-byte chunk. The
 // direction policy (u8_dir.hpp / u16_dir.hpp) validates and counts each chunk.
 //
-//  - validate / length: tiles are taken grid-stride; counts and the first
-//    flagged position are reduced per workgroup and added once at exit.
-//  - convert: tiles are taken in order from the workspace counter; one scan
-//    gives every chunk its offset inside the tile, a decoupled look-back gives
-//    the tile's offset in the output (device_common.hpp), then per sub-tile the
-//    chunks decode into LDS at their offsets, shifted so that LDS and global
-//    addresses agree modulo 16, and the sub-tile's output leaves in 16-byte
-//    stores.
+//  - validate / length: tiles are taken grid-stride (the next tile's loads
+//    are issued before the current tile's work, so they are in flight
+//    meanwhile) and staged in LDS with the 16 bytes on either side; counts and
+//    the first flagged position are reduced per workgroup and added once at
+//    exit.
+//  - convert: one workgroup per tile, and the tile stays in registers from
+//    the load to the output: the neighbouring dwords come from the adjacent
+//    lanes (DPP) and, across wave and sub-tile boundaries, through a few LDS
+//    words, so LDS holds only the output staging and the pair table and more
+//    workgroups fit a CU. One scan gives every chunk its offset inside the
+//    tile, a decoupled look-back gives the tile's offset in the output
+//    (device_common.hpp), then per sub-tile the chunks decode into LDS at
+//    their offsets, shifted so that LDS and global addresses agree modulo 16,
+//    and the sub-tile's output leaves in 16-byte stores.
 #pragma once
 
 #include "finish.hpp"
@@ -45,11 +49,23 @@ struct ScanShared {
     int flag;
 };
 
+// Output staging starts this many units into its buffer (see emit_tile); 16
+// units keep LDS and global addresses congruent modulo 16 bytes.
+constexpr unsigned int kStageFront = 16;
+
+// The dwords at the wave and sub-tile boundaries of a register-resident tile.
+template <int U>
+struct TileEdges {
+    unsigned int first[U][kWaves];   // first dword of each wave's part of sub-tile u
+    unsigned int last[U][kWaves];    // last dword of it
+    unsigned int pre, post;          // the dword just before the tile, just after it
+};
+
 template <class Dir, int U>
 struct ConvertShared {
-    alignas(16) unsigned int in[tile_words<U>()];
-    alignas(16) typename Dir::Out out[Dir::kStageUnits];
+    alignas(16) typename Dir::Out out[kStageFront + Dir::kStageUnits];
     alignas(16) unsigned char table[Dir::kNeedsTable ? 4096 : 16];
+    TileEdges<U> edges;
     unsigned int scan[U][kWaves];
     unsigned long long red[kWaves];
     unsigned long long prefix;
@@ -64,7 +80,8 @@ __device__ __forceinline__ void build_pair_table(unsigned char *table)
 }
 
 // Issue all loads of tile `tile`: U chunks per thread, plus (thread 0) the
-// granules just before and just after the tile. Unmasked: see stage_tile.
+// granules just before and just after the tile. Unmasked: stage_tile and
+// settle_tile zero what lies outside the document.
 template <int U>
 __device__ __forceinline__ void load_tile(const Doc &d, unsigned long long tile, uint4 q[U], uint4 &pre, uint4 &post)
 {
@@ -111,6 +128,55 @@ __device__ __forceinline__ void read_chunk(const unsigned int *in, int u, unsign
     x[5] = in[b + 4];
 }
 
+// A tile held in registers: this thread's chunk of every sub-tile. The
+// dwords just before and after a chunk come from the adjacent lanes (DPP)
+// each time the chunk is read, and at the ends of a wave from the boundary
+// dwords in LDS (settle_tile), so they hold no registers between uses.
+template <int U>
+struct TileRegs {
+    uint4 q[U];
+    const TileEdges<U> *e;
+
+    __device__ __forceinline__ void chunk(int u, unsigned int x[6]) const
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const unsigned int *lo = wave > 0 ? &e->last[u][wave - 1] : (u > 0 ? &e->last[u - 1][kWaves - 1] : &e->pre);
+        const unsigned int *hi = wave < kWaves - 1 ? &e->first[u][wave + 1] : (u + 1 < U ? &e->first[u + 1][0] : &e->post);
+        const unsigned int p = from_lower_lane(q[u].w), n = from_upper_lane(q[u].x);
+        const unsigned int pe = *lo, ne = *hi;   // same address in every lane: broadcast reads
+        x[0] = lane == 0 ? pe : p;
+        x[1] = q[u].x; x[2] = q[u].y; x[3] = q[u].z; x[4] = q[u].w;
+        x[5] = lane == 63 ? ne : n;
+    }
+};
+
+// After load_tile: zero the bytes outside the document (tiles at its edges
+// only) and post the boundary dwords to LDS. A barrier must follow before
+// the first TileRegs::chunk.
+template <int U>
+__device__ __forceinline__ void settle_tile(TileEdges<U> &e, const Doc &d, unsigned long long tile, TileRegs<U> &t,
+                                            uint4 pre, uint4 post)
+{
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    if (tv < d.off_b || tv + (unsigned long long)U * kSub > d.end_b) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            t.q[u] = mask_granule(t.q[u], tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (lane == 0)
+            e.first[u][wave] = t.q[u].x;
+        if (lane == 63)
+            e.last[u][wave] = t.q[u].w;
+    }
+    if (threadIdx.x == 0) {
+        e.pre = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b).w : 0u;
+        e.post = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b).x;
+    }
+}
+
 // Input units of the chunk at byte position cv that lie in the input.
 template <class Dir>
 __device__ __forceinline__ void chunk_range(const Doc &d, unsigned long long cv, unsigned int &lo, unsigned int &hi)
@@ -124,7 +190,7 @@ __device__ __forceinline__ void chunk_range(const Doc &d, unsigned long long cv,
 }
 
 // A tile whose chunks all lie inside the input with the input end beyond them
-// takes the FULL path (no per-byte range checks, no end-of-input check).
+// needs no count correction and no end-of-input check.
 template <int U>
 __device__ __forceinline__ bool tile_is_interior(const Doc &d, unsigned long long tile)
 {
@@ -132,42 +198,35 @@ __device__ __forceinline__ bool tile_is_interior(const Doc &d, unsigned long lon
     return tv >= d.off_b && tv + (unsigned long long)U * kSub < d.end_b;
 }
 
-// Truncation at the input's end, for the chunk at byte position cv (edge
-// tiles): lowers flag_min to the lead of a last character cut short.
-template <class Dir>
-__device__ __forceinline__ void end_check(const unsigned int x[6], const Doc &d, unsigned long long cv,
-                                          unsigned long long &flag_min)
+// Truncation at the input's end: thread 0 of the tile that holds the last
+// input unit lowers flag_min to the lead of a last character cut short (the
+// direction reads the last bytes from memory).
+template <class Dir, int U>
+__device__ __forceinline__ void end_check(const Doc &d, unsigned long long tile, unsigned long long &flag_min)
 {
-    if (cv < d.end_b && cv + kChunk >= d.end_b) {
-        const int j = Dir::end_truncation(x, (int)(d.end_b - cv));
-        if (j != kNoFlag) {
-            const unsigned long long pos = (cv - d.off_b) + (long long)j * Dir::kInUnit;
-            flag_min = pos < flag_min ? pos : flag_min;
-        }
+    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    if (threadIdx.x == 0 && d.end_b > tv && d.end_b <= tv + (unsigned long long)U * kSub) {
+        const long long j = Dir::end_truncation(d.base, d.off_b, d.end_b);
+        if (j >= 0 && (unsigned long long)j < flag_min)
+            flag_min = (unsigned long long)j;
     }
 }
 
 // Validation and counting of a staged tile. Returns the per-chunk counts in
 // c[] and lowers flag_min to the first flagged input byte position.
-template <class Dir, int U, bool COUNT, bool FULL>
-__device__ __forceinline__ void analyze_tile_as(const unsigned int *in, const unsigned char *table, const Doc &d,
-                                                unsigned long long tile, unsigned int c[U],
-                                                unsigned long long &flag_min)
+template <class Dir, int U, bool COUNT>
+__device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsigned char *table, const Doc &d,
+                                               unsigned long long tile, unsigned int c[U],
+                                               unsigned long long &flag_min)
 {
     const unsigned long long tv = tile * (unsigned long long)(U * kSub);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         unsigned int x[6];
-        read_chunk(in, u, x);
+        t.chunk(u, x);
         const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
-        unsigned int lo = 0, hi = kChunk / Dir::kInUnit;
-        int end_pos = -1;
-        if (!FULL) {
-            chunk_range<Dir>(d, cv, lo, hi);
-            end_pos = (cv < d.end_b && cv + kChunk >= d.end_b) ? (int)(d.end_b - cv) : -1;
-        }
         int f;
-        c[u] = Dir::template analyze<COUNT, FULL>(x, lo, hi, end_pos, table, &f);
+        c[u] = Dir::template analyze<COUNT>(x, table, &f);
         if (f != kNoFlag) {
             const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
             flag_min = pos < flag_min ? pos : flag_min;
@@ -178,10 +237,10 @@ __device__ __forceinline__ void analyze_tile_as(const unsigned int *in, const un
 }
 
 template <class Dir, int U, bool COUNT>
-__device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
+__device__ __forceinline__ void analyze_tile(const TileRegs<U> &t, const unsigned char *table, const Doc &d,
                                              unsigned long long tile, unsigned int c[U], unsigned long long &flag_min)
 {
-    analyze_tile_as<Dir, U, COUNT, true>(in, table, d, tile, c, flag_min);
+    analyze_chunks<Dir, U, COUNT>(t, table, d, tile, c, flag_min);
     if (!tile_is_interior<U>(d, tile)) {
         // Tiles at the input's edges hold zeros outside the input: each zero
         // counts as one unit (an ASCII byte or word), and the only flags they
@@ -190,18 +249,16 @@ __device__ __forceinline__ void analyze_tile(const unsigned int *in, const unsig
         // (the first-error decode in finish.hpp starts up to three bytes
         // before the flag and finds it).
         const unsigned long long tv = tile * (unsigned long long)(U * kSub);
-#pragma unroll 1
-        for (int u = 0; u < U; ++u) {
-            const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
-            if (COUNT) {
+        if (COUNT) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
                 unsigned int lo, hi;
                 chunk_range<Dir>(d, cv, lo, hi);
                 c[u] -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
             }
-            unsigned int x[6];
-            read_chunk(in, u, x);
-            end_check<Dir>(x, d, cv, flag_min);
         }
+        end_check<Dir, U>(d, tile, flag_min);
         const unsigned long long n_b = d.end_b - d.off_b;
         if (flag_min != ~0ull && flag_min >= n_b)
             flag_min = n_b - Dir::kInUnit;
@@ -227,24 +284,22 @@ __device__ __forceinline__ void scan_tile(const unsigned int *in, const unsigned
         read_chunk(in, u, x);
         const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
         int f;
-        unsigned int c = Dir::template analyze<COUNT, true>(x, 0u, kChunk / Dir::kInUnit, -1, table, &f);
+        unsigned int c = Dir::template analyze<COUNT>(x, table, &f);
         if (f != kNoFlag) {
             const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
             flag_min = pos < flag_min ? pos : flag_min;
         }
-        if (!interior) {
-            if (COUNT) {
-                unsigned int lo, hi;
-                chunk_range<Dir>(d, cv, lo, hi);
-                c -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
-            }
-            end_check<Dir>(x, d, cv, flag_min);
+        if (COUNT && !interior) {
+            unsigned int lo, hi;
+            chunk_range<Dir>(d, cv, lo, hi);
+            c -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
         }
         sum += c;
     }
     if (COUNT)
         total += sum;
     if (!interior) {
+        end_check<Dir, U>(d, tile, flag_min);
         const unsigned long long n_b = d.end_b - d.off_b;
         if (flag_min != ~0ull && flag_min >= n_b)
             flag_min = n_b - Dir::kInUnit;
@@ -373,9 +428,15 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
 
 // Output phase of a convert tile: per sub-tile, chunks decode into LDS at
 // their offsets (shifted so that LDS and global addresses agree modulo 16),
-// then the sub-tile's output leaves in aligned 16-byte stores.
-template <class Dir, int U, bool FULL>
-__device__ __forceinline__ void emit_tile(const unsigned int *in, typename Dir::Out *stage, const Doc &d,
+// then the sub-tile's output leaves in aligned 16-byte stores. `stage` points
+// kStageFront units into the staging buffer. Units outside the input are
+// zeros and decode like any other (one output unit each): those after the
+// input's end land past the sub-tile's output, which is never copied out;
+// those before its start (only in the first chunk of the first tile, fewer
+// than 16 bytes of alignment) land just before the chunk's output, in the
+// staging buffer's front margin.
+template <class Dir, int U>
+__device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Out *stage, const Doc &d,
                                           unsigned long long tile, const unsigned int excl[U], const unsigned int tot[U],
                                           unsigned long long pos, typename Dir::Out *dst)
 {
@@ -383,16 +444,13 @@ __device__ __forceinline__ void emit_tile(const unsigned int *in, typename Dir::
     // output units between dst and the 16-byte aligned address below it
     const unsigned int dst_mis = (unsigned int)(((uintptr_t)d.dst & 15u) / sizeof(Out));
     constexpr unsigned int G = 16 / sizeof(Out);
-    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    const unsigned int skip = (tile == 0 && threadIdx.x == 0) ? (unsigned int)(d.off_b / Dir::kInUnit) : 0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
         unsigned int x[6];
-        read_chunk(in, u, x);
-        unsigned int lo = 0, hi = kChunk / Dir::kInUnit;
-        if (!FULL)
-            chunk_range<Dir>(d, tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk, lo, hi);
-        Dir::template emit<FULL>(x, lo, hi, stage, shift + excl[u]);
+        t.chunk(u, x);
+        Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u));
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
         copy_out<Dir>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
@@ -423,14 +481,16 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 {
     using Out = typename Dir::Out;
     const int tid = threadIdx.x;
-    uint4 q[U], pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
-    load_tile<U>(d, tile, q, pre, post);
-    stage_tile<U>(s.in, d, tile, q, pre, post);
+    TileRegs<U> t;
+    t.e = &s.edges;
+    uint4 pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
+    load_tile<U>(d, tile, t.q, pre, post);
+    settle_tile<U>(s.edges, d, tile, t, pre, post);
     __syncthreads();
 
     unsigned long long my_flag = ~0ull;
     unsigned int c[U];
-    analyze_tile<Dir, U, MODE != kValidate>(s.in, s.table, d, tile, c, my_flag);
+    analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag);
     const unsigned long long tile_flag = block_min_u64(my_flag, s.red);
     unsigned int excl[U], tot[U];
     block_scan_multi<U>(c, excl, tot, s.scan);
@@ -462,10 +522,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     // failed call is unspecified: only flag-free (valid) tiles are decoded.
     if (MODE == kConvert && tile_flag == ~0ull) {
         Out *dst = reinterpret_cast<Out *>(d.dst);
-        if (tile_is_interior<U>(d, tile))
-            emit_tile<Dir, U, true>(s.in, s.out, d, tile, excl, tot, pos, dst);
-        else
-            emit_tile<Dir, U, false>(s.in, s.out, d, tile, excl, tot, pos, dst);
+        emit_tile<Dir, U>(t, s.out + kStageFront, d, tile, excl, tot, pos, dst);
     }
 }
 
@@ -504,8 +561,6 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
         wrap_clear(status, status_cap, &s.red[0]);
 }
 
-// The UTF-8 input side fits 128 registers (four waves per SIMD); the UTF-16
-// side needs more and runs at two.
 template <int U>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_convert_u8(
     Doc d, unsigned long long n_tiles, WsHeader *hdr, unsigned long long *status, unsigned long long status_cap,

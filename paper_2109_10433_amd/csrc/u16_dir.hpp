@@ -17,6 +17,8 @@
 
 namespace hu {
 
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ bool is_high(unsigned int w) { return (w & 0xFC00u) == 0xD800u; }
 __device__ __forceinline__ bool is_low(unsigned int w) { return (w & 0xFC00u) == 0xDC00u; }
 
@@ -46,23 +48,40 @@ struct U16Dir {
         return (x[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
     }
 
-    // [lo, hi): word positions of the chunk inside the input. Positions in
-    // the flag are in words relative to the chunk start.
-    template <bool COUNT, bool FULL>
-    __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], unsigned int lo, unsigned int hi,
-                                                           int /*end_pos*/, const unsigned char * /*table*/, int *flag)
+    // x[0..5] as for UTF-8 input (8 words per chunk, words outside the input
+    // read as zero). Positions in the flag are in words relative to the chunk
+    // start. Called by whole waves (the surrogate test below is a wave vote).
+    template <bool COUNT>
+    __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char * /*table*/,
+                                                           int *flag)
     {
+        // Waves without any word in D800..DFFF have nothing to flag; each
+        // word then takes 1 + (w >= 0x80) + (w >= 0x800) UTF-8 bytes. The two
+        // words of a dword are tested together as 16-bit halves.
+        u16x2 extra = {0, 0}, plain = {1, 1};
+        const u16x2 one = {1, 1}, sur = {0x1B, 0x1B};   // w >> 11 of D800..DFFF
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const u16x2 w = __builtin_bit_cast(u16x2, x[k]);
+            const u16x2 t11 = w >> 11;
+            if (COUNT)
+                extra += __builtin_elementwise_min(w >> 7, one) + __builtin_elementwise_min(t11, one);
+            plain = __builtin_elementwise_min(plain, __builtin_elementwise_min(t11 ^ sur, one));
+        }
+        if (!__any(__builtin_bit_cast(unsigned int, plain) != 0x00010001u)) {
+            *flag = kNoFlag;
+            return COUNT ? 8u + extra.x + extra.y : 0u;
+        }
         unsigned int count = 0;
         int f = kNoFlag;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j), pw = word(x, j - 1), nw = word(x, j + 1);
-            const bool in = FULL || ((unsigned int)j >= lo && (unsigned int)j < hi);
             const bool bad = (is_high(w) && !is_low(nw)) || (is_low(w) && !is_high(pw));
-            if (in && bad && f == kNoFlag)
+            if (bad && f == kNoFlag)
                 f = j;
             if (COUNT)
-                count += in ? utf8_bytes_of(w) : 0u;
+                count += utf8_bytes_of(w);
         }
         *flag = f;
         return count;
@@ -70,29 +89,26 @@ struct U16Dir {
 
     // A high surrogate in the last word is flagged by analyze itself (its
     // successor reads as zero): nothing to add at the end of the input.
-    __device__ __forceinline__ static int end_truncation(const unsigned int * /*x*/, int /*end_pos*/)
+    __device__ __forceinline__ static long long end_truncation(const uint8_t * /*base*/, unsigned long long /*off_b*/,
+                                                               unsigned long long /*end_b*/)
     {
-        return kNoFlag;
+        return -1;
     }
 
     // Only called for tiles without any flagged word: the output of a sub-tile
-    // then fits the staging buffer.
-    template <bool FULL>
-    __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
-                                                unsigned int o)
+    // then fits the staging buffer. Called by whole waves.
+    __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o)
     {
-        if (FULL) {
-            // words of three UTF-8 bytes or surrogates anywhere in the wave?
-            const bool wide = ((x[1] | x[2] | x[3] | x[4]) & 0xF800F800u) != 0;
-            if (!__any(wide)) {
-                emit_narrow(x, out, o);
-                return;
-            }
+        // words of three UTF-8 bytes or surrogates anywhere in the wave?
+        const bool wide = ((x[1] | x[2] | x[3] | x[4]) & 0xF800F800u) != 0;
+        if (!__any(wide)) {
+            emit_narrow(x, out, o);
+            return;
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j), nw = word(x, j + 1);
-            const unsigned int m = (FULL || ((unsigned int)j >= lo && (unsigned int)j < hi)) ? utf8_bytes_of(w) : 0u;
+            const unsigned int m = utf8_bytes_of(w);
             unsigned int b0, b1 = 0, b2 = 0, b3 = 0;
             if (m == 4) {
                 const unsigned int cp = 0x10000u + (((w & 0x3FFu) << 10) | (nw & 0x3FFu));

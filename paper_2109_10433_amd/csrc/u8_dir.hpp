@@ -103,18 +103,6 @@ __device__ __forceinline__ unsigned int not_cont(unsigned int x)
     return (y | (y << 1)) & 0x80808080u;
 }
 
-// 0xFF in every byte whose position 4k + b (b = 0..3) lies in [lo, hi)
-__device__ __forceinline__ unsigned int byte_range_mask(int k, unsigned int lo, unsigned int hi)
-{
-    unsigned int m = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        unsigned int pos = 4 * k + b;
-        m |= (pos >= lo && pos < hi) ? (0xFFu << (8 * b)) : 0u;
-    }
-    return m;
-}
-
 // Decode the character whose lead byte is the low byte of w (little-endian
 // window of the next four bytes) into one UTF-16 word or a surrogate pair.
 // Bit layouts: section 3 (7/11/16/21 payload bits, most significant first;
@@ -148,31 +136,57 @@ struct U8Dir {
     static constexpr unsigned int kStageUnits = kSub + 40;
 
     // x[0]: the 4 bytes before the chunk, x[1..4]: the chunk, x[5]: the 4
-    // bytes after. FULL: the whole chunk and its neighbours lie inside the
-    // input (then lo = 0, hi = 16, no end inside). Otherwise [lo, hi) are the
-    // positions of the chunk inside the input and `end_pos` is the position of
-    // the input end relative to the chunk start if it falls in (0, 16], else
-    // negative. Returns the number of UTF-16 words of the characters that
-    // start in the chunk (if COUNT) and sets *flag to the first flagged
-    // position relative to the chunk start (kNoFlag if none).
-    template <bool COUNT, bool FULL>
-    __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], unsigned int lo, unsigned int hi,
-                                                           int end_pos, const unsigned char *table, int *flag)
+    // bytes after (bytes outside the input read as zero). Returns the number
+    // of UTF-16 words of the characters that start in the chunk (if COUNT) and
+    // sets *flag to the first flagged position relative to the chunk start
+    // (kNoFlag if none). Truncation at the input's end is end_truncation's.
+    // Called by whole waves (the narrow test below is a wave vote).
+    template <bool COUNT>
+    __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char *table,
+                                                           int *flag)
     {
-        // per dword: bytes >= E0 and >= F0 (bit 7 of each byte)
-        unsigned int G[5], F[5];
+        // Waves with no byte >= E0 hold one- and two-byte characters only
+        // (or errors). There the rules of section 3 reduce to: a byte is a
+        // continuation exactly when the byte before it is a lead, and no lead
+        // is C0 or C1. That check needs no table; a wave that fails it goes
+        // through the general check below, which places the flag.
+        // per dword: bytes >= E0 (bit 7 of each byte)
+        unsigned int G[5];
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 5; ++k)
             G[k] = ge_e0(x[k]);
-            F[k] = G[k] & (x[k] << 3);
+        if (!__any(G[0] | G[1] | G[2] | G[3] | G[4])) {
+            unsigned int bad = 0, count = 0;
+            unsigned int lead_prev = x[0] & (x[0] << 1) & 0x80808080u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned int cur = x[k + 1];
+                const unsigned int hib = cur & 0x80808080u;
+                const unsigned int lead = hib & (cur << 1);   // C0..DF
+                const unsigned int cont = hib ^ lead;         // 80..BF
+                const unsigned int after_lead = __builtin_amdgcn_alignbyte(lead, lead_prev, 3);
+                // bit 7: payload bits 1..4 not all zero (false for C0, C1)
+                const unsigned int big = ((cur & 0x1E1E1E1Eu) + 0x7F7F7F7Fu) & 0x80808080u;
+                bad |= (cont ^ after_lead) | (lead & ~big);
+                if (COUNT)
+                    count += __popc(cont ^ 0x80808080u);
+                lead_prev = lead;
+            }
+            if (!__any(bad)) {
+                *flag = kNoFlag;
+                return count;
+            }
         }
+        // per dword: bytes >= F0
+        unsigned int F[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            F[k] = G[k] & (x[k] << 3);
         unsigned int count = 0;
         if (COUNT) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const unsigned int rm = FULL ? 0xFFFFFFFFu : byte_range_mask(k, lo, hi);
-                count += __popc(not_cont(x[k + 1]) & rm) + __popc(F[k + 1] & rm);
-            }
+            for (int k = 0; k < 4; ++k)
+                count += __popc(not_cont(x[k + 1])) + __popc(F[k + 1]);
         }
         int f = kNoFlag;
         const bool ascii = ((x[1] | x[2] | x[3] | x[4]) & 0x80808080u) == 0;
@@ -195,70 +209,47 @@ struct U8Dir {
                 // back is E0..FF or the byte three back is F0..FF
                 const unsigned int must = __builtin_amdgcn_alignbyte(G[k + 1], G[k], 2) |
                                           __builtin_amdgcn_alignbyte(F[k + 1], F[k], 1);
-                unsigned int flags = (e | ((e << 1) ^ must)) & 0x80808080u;
-                if (!FULL)
-                    flags &= byte_range_mask(k, lo, 32u);
+                const unsigned int flags = (e | ((e << 1) ^ must)) & 0x80808080u;
                 if (flags && f == kNoFlag)
                     f = 4 * k + (__builtin_ctz(flags) >> 3);
-            }
-        }
-        if (!FULL && end_pos > 0) {
-            // truncation: a lead among the last three bytes that needs more
-            // bytes than remain (bytes before the chunk come from x[0])
-#pragma unroll
-            for (int back = 3; back >= 1; --back) {
-                // bytes outside the input read as zero and never match
-                const int j = end_pos - back;   // >= -2
-                const int i = j + 4;            // index into the 24 bytes of x[0..5]
-                const unsigned int dw = i < 4 ? x[0] : i < 8 ? x[1] : i < 12 ? x[2] : i < 16 ? x[3] : x[4];
-                const unsigned int b = (dw >> (8 * (i & 3))) & 0xFFu;
-                const unsigned int need = b >= 0xF0u ? 4u : b >= 0xE0u ? 3u : b >= 0xC0u ? 2u : 1u;
-                if (need > (unsigned int)back) {
-                    if (j < f)
-                        f = j;
-                    break;
-                }
             }
         }
         *flag = f;
         return count;
     }
 
-    // A lead byte among the last three input bytes that needs more bytes than
-    // remain: its position (relative to the chunk start; the input ends at
-    // end_pos in (0, 16]), else kNoFlag. Bytes before the chunk come from x[0];
-    // bytes outside the input read as zero and never match.
-    __device__ __forceinline__ static int end_truncation(const unsigned int x[6], int end_pos)
+    // A lead among the last three bytes of the input that needs more bytes
+    // than remain (rule 2 at the input's end): its position relative to the
+    // input start, else -1. The input is [base + off_b, base + end_b); one
+    // thread reads its last bytes from memory.
+    __device__ __forceinline__ static long long end_truncation(const uint8_t *base, unsigned long long off_b,
+                                                               unsigned long long end_b)
     {
-#pragma unroll
-        for (int back = 3; back >= 1; --back) {
-            const int j = end_pos - back;   // >= -2
-            const int i = j + 4;            // index into the 24 bytes of x[0..5]
-            const unsigned int dw = i < 4 ? x[0] : i < 8 ? x[1] : i < 12 ? x[2] : i < 16 ? x[3] : x[4];
-            const unsigned int b = (dw >> (8 * (i & 3))) & 0xFFu;
+        for (unsigned int back = 3; back >= 1; --back) {
+            if (end_b < off_b + back)
+                continue;   // before the input
+            const unsigned int b = base[end_b - back];
             const unsigned int need = b >= 0xF0u ? 4u : b >= 0xE0u ? 3u : b >= 0xC0u ? 2u : 1u;
-            if (need > (unsigned int)back)
-                return j;
+            if (need > back)
+                return (long long)(end_b - back - off_b);
         }
-        return kNoFlag;
+        return -1;
     }
 
     // Writes the words of the characters that start in the chunk to out[o..].
     // Only called for tiles without any flagged byte, so the chunk is valid
     // UTF-8 (its last character may end in the next chunk) and the output of a
-    // sub-tile fits the staging buffer.
-    template <bool FULL>
-    __device__ __forceinline__ static void emit(const unsigned int x[6], unsigned int lo, unsigned int hi, Out *out,
-                                                unsigned int o)
+    // sub-tile fits the staging buffer. Called by whole waves.
+    __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o)
     {
         unsigned int lead[4];
         bool wide = false;   // a byte >= E0: three- or four-byte characters
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            lead[k] = not_cont(x[k + 1]) & (FULL ? 0xFFFFFFFFu : byte_range_mask(k, lo, hi));
+            lead[k] = not_cont(x[k + 1]);
             wide |= (ge_e0(x[k + 1]) & lead[k]) != 0;
         }
-        if (FULL && !__any(wide)) {
+        if (!__any(wide)) {
             emit_narrow(x, lead, out, o);
             return;
         }

@@ -140,6 +140,14 @@ __device__ unsigned long long lookback(unsigned long long *status, unsigned int 
     return sum;
 }
 
+// The same value, but opaque to the compiler: expressions of it are computed
+// anew instead of being reused from earlier (and kept in registers till then).
+__device__ __forceinline__ unsigned int opaque(unsigned int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // ---------------------------------------------------------------- lanes
 // Lane l receives lane l - 1's value (DPP wave shift; lane 0 receives 0).
 __device__ __forceinline__ unsigned int from_lower_lane(unsigned int v)

@@ -137,15 +137,24 @@ struct TileRegs {
     uint4 q[U];
     const TileEdges<U> *e;
 
+    // FRESH: hide the chunk's identity from the compiler, so that values it
+    // derived from the chunk in an earlier phase are recomputed instead of
+    // being kept in registers across the phases in between.
+    template <bool FRESH = false>
     __device__ __forceinline__ void chunk(int u, unsigned int x[6]) const
     {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
         const unsigned int *lo = wave > 0 ? &e->last[u][wave - 1] : (u > 0 ? &e->last[u - 1][kWaves - 1] : &e->pre);
         const unsigned int *hi = wave < kWaves - 1 ? &e->first[u][wave + 1] : (u + 1 < U ? &e->first[u + 1][0] : &e->post);
-        const unsigned int p = from_lower_lane(q[u].w), n = from_upper_lane(q[u].x);
+        x[1] = q[u].x; x[2] = q[u].y; x[3] = q[u].z; x[4] = q[u].w;
+        if (FRESH) {
+#pragma unroll
+            for (int k = 1; k <= 4; ++k)
+                x[k] = opaque(x[k]);
+        }
+        const unsigned int p = from_lower_lane(x[4]), n = from_upper_lane(x[1]);
         const unsigned int pe = *lo, ne = *hi;   // same address in every lane: broadcast reads
         x[0] = lane == 0 ? pe : p;
-        x[1] = q[u].x; x[2] = q[u].y; x[3] = q[u].z; x[4] = q[u].w;
         x[5] = lane == 63 ? ne : n;
     }
 };
@@ -250,9 +259,11 @@ __device__ __forceinline__ void analyze_tile(const TileRegs<U> &t, const unsigne
         // before the flag and finds it).
         const unsigned long long tv = tile * (unsigned long long)(U * kSub);
         if (COUNT) {
+            // chunk positions recomputed here rather than kept live since the loads
+            const unsigned int tid = opaque(threadIdx.x);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
+                const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)tid * kChunk;
                 unsigned int lo, hi;
                 chunk_range<Dir>(d, cv, lo, hi);
                 c[u] -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
@@ -449,7 +460,7 @@ __device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Ou
     for (int u = 0; u < U; ++u) {
         const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
         unsigned int x[6];
-        t.chunk(u, x);
+        t.template chunk<true>(u, x);
         Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u));
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();

@@ -283,22 +283,6 @@ struct U8Dir {
     __device__ __forceinline__ static void emit_narrow(const unsigned int x[6], const unsigned int lead[4], Out *out,
                                                        unsigned int o)
     {
-        unsigned int W[8];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const unsigned int a = x[k + 1];
-            const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);   // next bytes
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
-                const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
-                const unsigned int n2 = __builtin_amdgcn_perm(0u, n, sel);
-                // bits 6..10 from the lead's low five bits, bits 0..5 from the next byte
-                const unsigned int two = (((a2 << 6) & 0x07C007C0u) | (n2 & 0x003F003Fu));
-                const unsigned int m = ((a2 >> 7) & 0x00010001u) * 0xFFFFu;   // halves with b >= 0x80
-                W[2 * k + h] = (two & m) | (a2 & ~m);
-            }
-        }
         // first slot of each dword's characters
         unsigned int first[4];
         first[0] = o;
@@ -308,6 +292,19 @@ struct U8Dir {
         char *base = reinterpret_cast<char *>(out);
 #pragma unroll
         for (int k = 3; k >= 0; --k) {
+            const unsigned int a = x[k + 1];
+            const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);   // next bytes
+            unsigned int W[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
+                const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
+                const unsigned int n2 = __builtin_amdgcn_perm(0u, n, sel);
+                // bits 6..10 from the lead's low five bits, bits 0..5 from the next byte
+                const unsigned int two = (((a2 << 6) & 0x07C007C0u) | (n2 & 0x003F003Fu));
+                const unsigned int m = ((a2 >> 7) & 0x00010001u) * 0xFFFFu;   // halves with b >= 0x80
+                W[h] = (two & m) | (a2 & ~m);
+            }
             // byte b of incl: leads among bytes 0..b of this dword
             const unsigned int q = lead[k] >> 7;
             const unsigned int s1 = q + (q << 8);
@@ -316,7 +313,7 @@ struct U8Dir {
 #pragma unroll
             for (int b = 3; b >= 0; --b) {
                 const unsigned int addr = a0 + 2u * ((incl >> (8 * b)) & 0xFFu);
-                const unsigned int wv = W[2 * k + (b >> 1)];
+                const unsigned int wv = W[b >> 1];
                 unsigned short *p = reinterpret_cast<unsigned short *>(base + addr);
                 const unsigned short v = (unsigned short)((b & 1) ? (wv >> 16) : wv);
                 if (k == 0 && b == 0) {

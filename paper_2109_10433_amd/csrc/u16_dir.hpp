@@ -100,11 +100,25 @@ struct U16Dir {
     __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o)
     {
         // words of three UTF-8 bytes or surrogates anywhere in the wave?
-        const bool wide = ((x[1] | x[2] | x[3] | x[4]) & 0xF800F800u) != 0;
-        if (!__any(wide)) {
-            emit_narrow(x, out, o);
+        const unsigned int all = x[1] | x[2] | x[3] | x[4];
+        if (!__any((all & 0xF800F800u) != 0)) {
+            emit_direct<2>(x, out, o);
             return;
         }
+        bool sur = false;
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            // a 16-bit half equal to 0xD800 after masking: a surrogate
+            const unsigned int v = (x[k] & 0xF800F800u) ^ 0xD800D800u;
+            sur |= ((v - 0x00010001u) & ~v & 0x80008000u) != 0;
+        }
+        if (!__any(sur)) {
+            emit_direct<3>(x, out, o);
+            return;
+        }
+        // Surrogates in the wave: one word at a time (text dense in pairs has
+        // a high word and an empty low word per character, where a branch-free
+        // form would store four bytes for every word).
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j), nw = word(x, j + 1);
@@ -136,25 +150,49 @@ struct U16Dir {
         }
     }
 
-    // Only words below U+0800 in the wave (the paper's section 5 cases of one
-    // and two output bytes): byte 0 is w (w < 0x80) or 0xC0 | w >> 6, byte 1 is
-    // 0x80 | (w & 0x3F). Both are stored for every word, words in ascending
-    // order, at the word's output offset: a one-byte word's second byte lands
-    // on the next word's first byte, which the next word overwrites. The
-    // chunk's last word stores its second byte only when it has one (it must
-    // not spill into the next thread's output).
-    __device__ __forceinline__ static void emit_narrow(const unsigned int x[6], Out *out, unsigned int o)
+    // Encoding without a branch per word, for waves whose words need at most
+    // MAXB bytes: 2 is the paper's section 5 cases of one and two output
+    // bytes, 3 adds three-byte words (no surrogates). Bytes of a word w:
+    // b0 = w (w < 0x80), 0xC0 | w >> 6 (w < 0x800) or 0xE0 | w >> 12; the
+    // following bytes 0x80 | six bits each, most significant first. MAXB
+    // bytes are stored for every word, words in ascending order, at the
+    // word's output offset: bytes past a word's length land where the next
+    // words start, and those overwrite them. Nothing may spill past the
+    // chunk's output (the next thread's): the last MAXB - 1 words store a
+    // byte only where the chunk's remaining words still reach (words before
+    // them are followed by at least MAXB - 1 words of at least one byte).
+    template <int MAXB>
+    __device__ __forceinline__ static void emit_direct(const unsigned int x[6], Out *out, unsigned int o)
     {
+        static_assert(MAXB == 2 || MAXB == 3, "no surrogates");
+        constexpr int kSafe = 9 - MAXB;
+        unsigned int len[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j);
-            const bool two = w >= 0x80u;
-            const unsigned int b0 = two ? (0xC0u | (w >> 6)) : w;
-            const unsigned int b1 = 0x80u | (w & 0x3Fu);
-            out[o] = (Out)b0;
-            if (j < 7 || two)
-                out[o + 1] = (Out)b1;
-            o += two ? 2u : 1u;
+            len[j] = 1u + (w >= 0x80u ? 1u : 0u) + (MAXB == 3 && w >= 0x800u ? 1u : 0u);
+        }
+        // reach[j]: output bytes of words j..7 (only j >= kSafe matter)
+        unsigned int reach[8];
+        reach[7] = len[7];
+#pragma unroll
+        for (int j = 6; j >= 0; --j)
+            reach[j] = reach[j + 1] + len[j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const unsigned int w = word(x, j);
+            const unsigned int n = len[j];
+            const bool three = n == 3u;
+            unsigned int b[3];
+            b[0] = three ? (0xE0u | (w >> 12)) : n == 2u ? (0xC0u | (w >> 6)) : w;
+            b[1] = 0x80u | ((three ? (w >> 6) : w) & 0x3Fu);
+            b[2] = 0x80u | (w & 0x3Fu);
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i) {
+                if (j < kSafe || (unsigned int)i < reach[j])
+                    out[o + i] = (Out)b[i];
+            }
+            o += n;
         }
     }
 };

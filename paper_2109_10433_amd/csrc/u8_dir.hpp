@@ -243,16 +243,25 @@ struct U8Dir {
     __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o)
     {
         unsigned int lead[4];
-        bool wide = false;   // a byte >= E0: three- or four-byte characters
+        bool wide = false, pairs = false;   // bytes >= E0, bytes >= F0
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             lead[k] = not_cont(x[k + 1]);
-            wide |= (ge_e0(x[k + 1]) & lead[k]) != 0;
+            const unsigned int g = ge_e0(x[k + 1]);
+            wide |= g != 0;
+            pairs |= (g & (x[k + 1] << 3)) != 0;
         }
         if (!__any(wide)) {
-            emit_narrow(x, lead, out, o);
+            emit_direct<2>(x, lead, out, o);
             return;
         }
+        if (!__any(pairs)) {
+            emit_direct<3>(x, lead, out, o);
+            return;
+        }
+        // Surrogate pairs in the wave: one character at a time. (Text dense in
+        // four-byte characters has few leads per chunk; this loop runs once
+        // per lead, where a branch-free form would store at every byte.)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             unsigned int l = lead[k];
@@ -270,19 +279,26 @@ struct U8Dir {
         }
     }
 
-    // Only one- and two-byte characters in the wave (the first case of the
-    // paper's Algorithm "core component"). The word at byte position p is b
-    // (b < 0x80) or ((b & 0x1F) << 6) | (next & 0x3F) for a lead b >= 0xC0;
-    // words are formed two per register (16-bit halves) for all 16 positions,
-    // junk at continuation bytes. Every position then stores its word without
-    // a branch, positions in descending order, at the slot of the last lead at
-    // or before it: a continuation byte's junk lands in the slot of its lead,
-    // which the lead (stored later) overwrites. Only byte 0 can precede the
-    // chunk's first lead (a 2-byte character begun in the previous chunk); it
-    // stores only when it is a lead.
-    __device__ __forceinline__ static void emit_narrow(const unsigned int x[6], const unsigned int lead[4], Out *out,
+    // Decoding without a branch per character, for waves whose characters
+    // have at most MAXB bytes: 2 is the first case of the paper's Algorithm
+    // "core component", 3 its second (one 16-bit word per character). The
+    // word at byte position p, as if p held a lead b (bit layouts of section
+    // 3): b < 0x80: b;  C0..DF: ((b & 0x1F) << 6) | (n1 & 0x3F);  E0..EF:
+    // ((b & 0x0F) << 12) | ((n1 & 0x3F) << 6) | (n2 & 0x3F), with n1, n2 the
+    // following bytes. Words are formed two positions per register (16-bit
+    // halves) for all 16 positions, junk at continuation bytes. Every position
+    // then stores its word without a branch, positions in descending order, at
+    // the slot of the last lead at or before it: a continuation byte's junk
+    // lands in the slot of its lead (or of the character before), which that
+    // character, stored later, overwrites. The first bytes of the chunk (up to
+    // three, whatever MAXB) can precede its first lead (the rest of a
+    // character begun in the previous chunk); they store only when a lead is
+    // at or before them.
+    template <int MAXB>
+    __device__ __forceinline__ static void emit_direct(const unsigned int x[6], const unsigned int lead[4], Out *out,
                                                        unsigned int o)
     {
+        static_assert(MAXB == 2 || MAXB == 3, "one word per character");
         // first slot of each dword's characters
         unsigned int first[4];
         first[0] = o;
@@ -293,17 +309,26 @@ struct U8Dir {
 #pragma unroll
         for (int k = 3; k >= 0; --k) {
             const unsigned int a = x[k + 1];
-            const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);   // next bytes
+            const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);    // next bytes
+            const unsigned int n2 = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 2);   // the bytes after
             unsigned int W[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
                 const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
-                const unsigned int n2 = __builtin_amdgcn_perm(0u, n, sel);
+                const unsigned int b2 = __builtin_amdgcn_perm(0u, n, sel);
                 // bits 6..10 from the lead's low five bits, bits 0..5 from the next byte
-                const unsigned int two = (((a2 << 6) & 0x07C007C0u) | (n2 & 0x003F003Fu));
+                const unsigned int two = (((a2 << 6) & 0x07C007C0u) | (b2 & 0x003F003Fu));
                 const unsigned int m = ((a2 >> 7) & 0x00010001u) * 0xFFFFu;   // halves with b >= 0x80
-                W[h] = (two & m) | (a2 & ~m);
+                unsigned int w = (two & m) | (a2 & ~m);
+                if (MAXB >= 3) {
+                    const unsigned int c2 = __builtin_amdgcn_perm(0u, n2, sel);
+                    const unsigned int three =
+                        ((a2 << 12) & 0xF000F000u) | ((b2 << 6) & 0x0FC00FC0u) | (c2 & 0x003F003Fu);
+                    const unsigned int m3 = ((a2 >> 5) & (a2 >> 6) & m & 0x00010001u) * 0xFFFFu;   // b >= 0xE0
+                    w = (three & m3) | (w & ~m3);
+                }
+                W[h] = w;
             }
             // byte b of incl: leads among bytes 0..b of this dword
             const unsigned int q = lead[k] >> 7;
@@ -313,15 +338,14 @@ struct U8Dir {
 #pragma unroll
             for (int b = 3; b >= 0; --b) {
                 const unsigned int addr = a0 + 2u * ((incl >> (8 * b)) & 0xFFu);
-                const unsigned int wv = W[b >> 1];
                 unsigned short *p = reinterpret_cast<unsigned short *>(base + addr);
-                const unsigned short v = (unsigned short)((b & 1) ? (wv >> 16) : wv);
-                if (k == 0 && b == 0) {
-                    if (q & 1u)
-                        *p = v;
-                } else {
+                const unsigned short v = (unsigned short)((b & 1) ? (W[b >> 1] >> 16) : W[b >> 1]);
+                // chunk start: positions before the first lead store nothing
+                // (up to three: the chunk before may end with any lead, even
+                // in a wave that took another path)
+                const bool guard = k == 0 && b < 3;
+                if (!guard || ((incl >> (8 * b)) & 0xFFu) != 0)
                     *p = v;
-                }
             }
         }
     }

@@ -123,6 +123,48 @@ def test_small_sizes_and_offsets():
             check_u16_all(text.u16[:n], offset, out_offset=offset % 5)
 
 
+@pytest.mark.parametrize("profile", ["latin", "cyrillic", "cjk", "emoji"])
+def test_decode_paths_at_edges(profile):
+    """Each decode path (waves of one/two-byte characters, of up to three
+    bytes, the general one) at the input's edges: sizes around chunk, wave,
+    sub-tile and tile boundaries, cut at character starts, unaligned starts."""
+    text = wl.make_text(profile, 70_000, wl.rng_for("paths", profile))
+    sizes = (0, 1, 2, 3, 15, 16, 17, 255, 1023, 1024, 1025, 4095, 4096, 4097,
+             16383, 16384, 16385, 24577, 65533, 65541)
+    s8, s16 = text.char_starts_u8, text.char_starts_u16
+    for offset in (0, 5, 15):
+        say(profile, "utf8 edge sizes at offset", offset)
+        for n in sizes:
+            m = int(s8[np.searchsorted(s8, n, side="right") - 1]) if n < text.u8.size else text.u8.size
+            check_u8_all(text.u8[:m], offset, out_offset=2 * (offset % 3))
+    for offset in (0, 6, 14):
+        say(profile, "utf16 edge sizes at offset", offset)
+        for n in sizes:
+            m = int(s16[np.searchsorted(s16, n, side="right") - 1]) if n < text.u16.size else text.u16.size
+            check_u16_all(text.u16[:m], offset, out_offset=offset % 5)
+
+
+def test_characters_split_across_wave_boundaries():
+    """A three- or four-byte character that starts in the last chunk of a wave
+    and ends in the next wave, whose own characters are all shorter (that wave
+    decodes on a path for short characters and must still leave the split
+    character's words alone), at wave, sub-tile and tile boundaries."""
+    fillers = {"ascii": "abcdefgh", "two-byte": "aжbвcд", "three-byte": "a中b文"}
+    for boundary in (1024, 4096, 16384):
+        for ch in ("中", "😀"):
+            for back in range(1, len(ch.encode()) ):
+                for name, fill in fillers.items():
+                    if len(ch.encode()) <= max(len(c.encode()) for c in fill):
+                        continue
+                    head = "x" * (boundary - back)
+                    text = head + ch + (fill * (3000 // len(fill)))
+                    u8 = np.frombuffer(text.encode("utf-8"), np.uint8)
+                    u16 = np.frombuffer(text.encode("utf-16-le"), np.uint16)
+                    say("split", repr(ch), "at", boundary, "-", back, "then", name)
+                    check_u8_all(u8)
+                    check_u16_all(u16)
+
+
 def test_power_of_two_sizes():
     text = wl.make_text("mix", (1 << 17) + 64, wl.rng_for("pow2"))
     for k in range(4, 18):

@@ -228,20 +228,26 @@ __device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsig
                                                unsigned long long tile, unsigned int c[U],
                                                unsigned long long &flag_min)
 {
-    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    // first flag as a 32-bit position inside the tile (no 64-bit chunk
+    // positions kept live across the sub-tiles)
+    unsigned int rel_min = ~0u;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         unsigned int x[6];
         t.chunk(u, x);
-        const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
         int f;
         c[u] = Dir::template analyze<COUNT>(x, table, &f);
         if (f != kNoFlag) {
-            const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
-            flag_min = pos < flag_min ? pos : flag_min;
+            const unsigned int rel = (unsigned int)(u * kSub) + threadIdx.x * kChunk + (unsigned int)f * Dir::kInUnit;
+            rel_min = rel < rel_min ? rel : rel_min;
         }
         // keep sub-tiles from being interleaved by the scheduler (register pressure)
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if (rel_min != ~0u) {
+        // zeros before the input are never flagged: the position is >= off_b
+        const unsigned long long pos = tile * (unsigned long long)(U * kSub) + rel_min - d.off_b;
+        flag_min = pos < flag_min ? pos : flag_min;
     }
 }
 
@@ -356,6 +362,8 @@ __device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsign
             all += x;
         }
         excl[u] += before;
+        // done here, not sunk past the look-back with the loaded totals kept live
+        asm volatile("" : "+v"(excl[u]) :: "memory");
         tot[u] = __builtin_amdgcn_readfirstlane(all);   // uniform: keep it in a scalar register
     }
 }
@@ -581,7 +589,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 }
 
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_convert_u16(Doc d, unsigned long long n_tiles, WsHeader *hdr,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_convert_u16(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                                         unsigned long long *status, unsigned long long status_cap,
                                                         hu_result *out)
 {

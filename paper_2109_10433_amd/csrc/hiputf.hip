@@ -58,12 +58,11 @@ int max_resident_blocks(const void *kernel)
 constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 bits
 
 // sub-tiles per tile (tile = U x 4 KiB of input)
-// Sub-tiles per convert tile. Measured on 256 MiB inputs: 5 (72 registers,
-// 7 waves per SIMD) beats 4 (62 registers, 8 waves) by fewer look-backs on
-// one- and two-byte text and loses a little on text dense in pairs; 6 and
-// more lose occupancy faster than they save look-backs.
+// Sub-tiles per convert tile: the largest that still fit 64 registers (eight
+// waves per SIMD); bigger tiles mean fewer look-backs per byte. UTF-8 input
+// at 6 would spill; UTF-16 input fits 6 when held to eight waves.
 constexpr int kUConvert8 = 5;
-constexpr int kUConvert16 = 5;
+constexpr int kUConvert16 = 6;
 constexpr int kUScan = 8;
 
 struct KernelChoice {

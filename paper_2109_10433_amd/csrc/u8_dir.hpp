@@ -96,11 +96,11 @@ __device__ const PairTable g_pair_table = make_pair_table();
 // bit 7 of each byte of the result is set iff that byte of x is >= 0xE0 / 0xF0
 __device__ __forceinline__ unsigned int ge_e0(unsigned int x) { return x & (x << 1) & (x << 2) & 0x80808080u; }
 __device__ __forceinline__ unsigned int ge_f0(unsigned int x) { return ge_e0(x) & (x << 3); }
-// bit 7 of each byte set iff that byte of x equals c
-__device__ __forceinline__ unsigned int bytes_equal(unsigned int x, unsigned int c)
+// bit 7 of each byte set iff bits 1..4 of that byte are not all zero (for a
+// lead C0..DF: false exactly for C0 and C1, the overlong two-byte leads)
+__device__ __forceinline__ unsigned int payload_nonzero(unsigned int x)
 {
-    const unsigned int t = x ^ (c * 0x01010101u);
-    return ~(((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
+    return ((x & 0x1E1E1E1Eu) + 0x7F7F7F7Fu) & 0x80808080u;
 }
 // bit 7 of each byte set iff that byte is not a continuation byte (10xxxxxx)
 __device__ __forceinline__ unsigned int not_cont(unsigned int x)
@@ -153,9 +153,13 @@ struct U8Dir {
     {
         // Waves with no byte >= E0 hold one- and two-byte characters only
         // (or errors). There the rules of section 3 reduce to: a byte is a
-        // continuation exactly when the byte before it is a lead, and no lead
-        // is C0 or C1. That check needs no table; a wave that fails it goes
-        // through the general check below, which places the flag.
+        // continuation exactly when the byte before it is a lead, and the byte
+        // before it is not C0 or C1. That check needs no table; a wave that
+        // fails it goes through the general check below, which places the
+        // flag. Every test looks at the byte and the one before it, as the
+        // general check does, so a chunk passes exactly when that check
+        // would flag nothing in it that comes first (a pair split across two
+        // chunks is judged by the second, in either check).
         // per dword: bytes >= E0 (bit 7 of each byte)
         unsigned int G[5];
 #pragma unroll
@@ -164,69 +168,31 @@ struct U8Dir {
         if (!__any(G[0] | G[1] | G[2] | G[3] | G[4])) {
             unsigned int bad = 0, count = 0;
             unsigned int lead_prev = x[0] & (x[0] << 1) & 0x80808080u;
+            unsigned int c01_prev = lead_prev & ~payload_nonzero(x[0]);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const unsigned int cur = x[k + 1];
                 const unsigned int hib = cur & 0x80808080u;
                 const unsigned int lead = hib & (cur << 1);   // C0..DF
                 const unsigned int cont = hib ^ lead;         // 80..BF
-                const unsigned int after_lead = __builtin_amdgcn_alignbyte(lead, lead_prev, 3);
-                // bit 7: payload bits 1..4 not all zero (false for C0, C1)
-                const unsigned int big = ((cur & 0x1E1E1E1Eu) + 0x7F7F7F7Fu) & 0x80808080u;
-                bad |= (cont ^ after_lead) | (lead & ~big);
+                const unsigned int c01 = lead & ~payload_nonzero(cur);   // C0, C1
+                bad |= (cont ^ __builtin_amdgcn_alignbyte(lead, lead_prev, 3)) |
+                       __builtin_amdgcn_alignbyte(c01, c01_prev, 3);
                 if (COUNT)
                     count += __popc(cont ^ 0x80808080u);
                 lead_prev = lead;
+                c01_prev = c01;
             }
             if (!__any(bad)) {
                 *flag = kNoFlag;
                 return count;
             }
         }
-        unsigned int four = 0;   // bytes >= F0 anywhere in x[0..4]
-#pragma unroll
-        for (int k = 0; k < 5; ++k)
-            four |= G[k] & (x[k] << 3);
-        // Waves with no byte >= F0 hold characters of at most three bytes (or
-        // errors). There the rules reduce to: a byte is a continuation exactly
-        // when the byte before it is a lead or the byte two before is a
-        // three-byte lead; no lead is C0 or C1; E0 is not followed by 80..9F
-        // (overlong) nor ED by A0..BF (surrogates). Again no table; a wave that
-        // fails goes through the general check.
-        if (!__any(four)) {
-            unsigned int bad = 0, count = 0;
-            unsigned int lead_prev = x[0] & (x[0] << 1) & 0x80808080u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                // (opaque: shifts recomputed here, not kept from the votes above)
-                const unsigned int cur = opaque(x[k + 1]);
-                const unsigned int hib = cur & 0x80808080u;
-                const unsigned int lead = hib & (cur << 1);   // C0..EF
-                const unsigned int cont = hib ^ lead;         // 80..BF
-                const unsigned int expect = __builtin_amdgcn_alignbyte(lead, lead_prev, 3) |
-                                            __builtin_amdgcn_alignbyte(G[k + 1], G[k], 2);
-                const unsigned int big = ((cur & 0x1E1E1E1Eu) + 0x7F7F7F7Fu) & 0x80808080u;
-                const unsigned int p1 = __builtin_amdgcn_alignbyte(cur, x[k], 3);   // byte before each byte
-                const unsigned int b5 = (cur << 2) & 0x80808080u;   // A0..BF among continuations
-                bad = opaque(bad | (cont ^ expect) | (lead & ~G[k + 1] & ~big) | (bytes_equal(p1, 0xE0u) & ~b5) |
-                             (bytes_equal(p1, 0xEDu) & b5));
-                if (COUNT)
-                    count += __popc(cont ^ 0x80808080u);
-                lead_prev = lead;
-                // one dword at a time: the registers of four in flight would
-                // cost the kernel a wave per SIMD
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (!__any(bad)) {
-                *flag = kNoFlag;
-                return count;
-            }
-        }
-        // per dword: bytes >= F0 (recomputed here, not held through the tier above)
+        // per dword: bytes >= F0
         unsigned int F[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k)
-            F[k] = G[k] & (opaque(x[k]) << 3);
+            F[k] = G[k] & (x[k] << 3);
         unsigned int count = 0;
         if (COUNT) {
 #pragma unroll

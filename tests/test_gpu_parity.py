@@ -165,6 +165,33 @@ def test_characters_split_across_wave_boundaries():
                     check_u16_all(u16)
 
 
+@pytest.mark.parametrize("profile", ["latin", "cyrillic", "cjk"])
+def test_errors_in_short_character_waves(profile):
+    """Errors inside text of one/two-byte (Latin, Cyrillic) or up to
+    three-byte (CJK) characters, where whole waves take the table-free checks:
+    each ill-formed sequence must send its wave to the general check and come
+    out with the oracle's kind and position, at chunk and wave boundaries."""
+    text = wl.make_text(profile, 32 * 1024, wl.rng_for("short-waves", profile))
+    seqs = [[0xC0, 0x80], [0xC1, 0xBF], [0xC3, 0x41], [0x80], [0xBF, 0x80], [0xC3, 0xA9, 0xA9],
+            [0xE0, 0x80, 0x80], [0xE0, 0x9F, 0xBF], [0xED, 0xA0, 0x80], [0xED, 0xBF, 0xBF],
+            [0xE4, 0xB8, 0x41], [0xE4, 0x41], [0xE4, 0xB8, 0xAD, 0x80], [0xEF, 0xBF]]
+    starts = text.char_starts_u8[:-1]
+    rng = np.random.default_rng(11)
+    spots = [1024 * k + d for k in (3, 7, 19) for d in (-3, -1, 0, 1, 2)] + [16 * 5 + 15]
+    spots += [int(x) for x in rng.integers(0, text.u8.size - 8, 6)]
+    for seq in seqs:
+        say(profile, "error sequence", bytes(seq).hex())
+        for spot in spots:
+            p = int(starts[np.searchsorted(starts, spot)])      # a character start at or after the spot
+            data = text.u8.copy()
+            data[p:p + len(seq)] = seq
+            j = p + len(seq)
+            while j < data.size and (data[j] & 0xC0) == 0x80:  # no leftover continuations
+                data[j] = 0x20
+                j += 1
+            check_u8_all(data)
+
+
 def test_power_of_two_sizes():
     text = wl.make_text("mix", (1 << 17) + 64, wl.rng_for("pow2"))
     for k in range(4, 18):

@@ -109,6 +109,21 @@ hu_result utf8_length_from_utf16le(const uint16_t *src, size_t n_words, void *st
 hu_result convert_utf16le_to_utf8(const uint16_t *src, size_t n_words,
                                   uint8_t *dst, size_t dst_cap_bytes, void *stream);
 
+/* Non-validating conversions, for input known to be valid (section 4's
+ * non-validating transcoder, and its UTF-16 counterpart of section 5): the
+ * same output and count as the validating calls on valid input, without the
+ * validation work. On invalid input the result and the contents of
+ * dst[0, cap) are unspecified (a tile whose counts do not fit the decoder's
+ * staging is left undecoded), but the call completes, never writes outside
+ * [dst, dst + cap) and still reports HU_ERR_OUTPUT_TOO_SMALL when its count
+ * exceeds cap. Arguments, capacities and argument errors as for
+ * convert_utf8_to_utf16le / convert_utf16le_to_utf8; workspace as for the op
+ * HU_OP_CONVERT_UTF8_TO_UTF16LE / HU_OP_CONVERT_UTF16LE_TO_UTF8. */
+hu_result convert_valid_utf8_to_utf16le(const uint8_t *src, size_t n_bytes,
+                                        uint16_t *dst, size_t dst_cap_words, void *stream);
+hu_result convert_valid_utf16le_to_utf8(const uint16_t *src, size_t n_words,
+                                        uint8_t *dst, size_t dst_cap_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Asynchronous calls (allocate nothing, never synchronise, safe to record
  * into a HIP graph). Same operations as above; the result is written to the
@@ -151,6 +166,12 @@ int utf8_length_from_utf16le_async(const uint16_t *src, size_t n_words, hu_resul
 int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst,
                                   size_t dst_cap_bytes, hu_result *d_result,
                                   void *ws, size_t ws_bytes, void *stream);
+int convert_valid_utf8_to_utf16le_async(const uint8_t *src, size_t n_bytes, uint16_t *dst,
+                                        size_t dst_cap_words, hu_result *d_result,
+                                        void *ws, size_t ws_bytes, void *stream);
+int convert_valid_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst,
+                                        size_t dst_cap_bytes, hu_result *d_result,
+                                        void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many documents of any lengths, each with its own operation (any of

@@ -55,6 +55,8 @@ for _name, _args in [
     ("validate_utf16le", [_p, _sz, _p]),
     ("utf8_length_from_utf16le", [_p, _sz, _p]),
     ("convert_utf16le_to_utf8", [_p, _sz, _p, _sz, _p]),
+    ("convert_valid_utf8_to_utf16le", [_p, _sz, _p, _sz, _p]),
+    ("convert_valid_utf16le_to_utf8", [_p, _sz, _p, _sz, _p]),
 ]:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = HuResult
@@ -65,6 +67,8 @@ for _name, _args in [
     ("validate_utf16le_async", [_p, _sz, _p, _p, _sz, _p]),
     ("utf8_length_from_utf16le_async", [_p, _sz, _p, _p, _sz, _p]),
     ("convert_utf16le_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+    ("convert_valid_utf8_to_utf16le_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+    ("convert_valid_utf16le_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
 ]:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _i
@@ -117,6 +121,8 @@ EXPORTED = EXPORTED_BATCH + EXPORTED_SERVER + [
     "validate_utf16le", "utf8_length_from_utf16le", "convert_utf16le_to_utf8",
     "validate_utf8_async", "utf16_length_from_utf8_async", "convert_utf8_to_utf16le_async",
     "validate_utf16le_async", "utf8_length_from_utf16le_async", "convert_utf16le_to_utf8_async",
+    "convert_valid_utf8_to_utf16le", "convert_valid_utf16le_to_utf8",
+    "convert_valid_utf8_to_utf16le_async", "convert_valid_utf16le_to_utf8_async",
     "hu_workspace_bytes", "hu_workspace_init", "hu_error_name", "hu_shutdown",
 ]
 
@@ -160,16 +166,18 @@ def utf16_length_from_utf8(src: torch.Tensor, stream=None) -> Result:
         return _res(lib.utf16_length_from_utf8(src.data_ptr(), src.numel(), stream_handle(stream)))
 
 
-def convert_utf8_to_utf16le(src: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+def convert_utf8_to_utf16le(src: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                            validate: bool = True):
     """Returns (int16 tensor holding the UTF-16LE words, Result). With `out`
-    the words go there (capacity = out.numel()) and `out` is returned whole."""
+    the words go there (capacity = out.numel()) and `out` is returned whole.
+    validate=False: the non-validating call, for input known to be valid."""
     _check(src, _U8, "src")
+    fn = lib.convert_utf8_to_utf16le if validate else lib.convert_valid_utf8_to_utf16le
     with torch.cuda.device(src.device):
         dst = out if out is not None else torch.empty(max(src.numel(), 1), dtype=torch.int16, device=src.device)
         _check(dst, _U16, "out")
-        r = _res(lib.convert_utf8_to_utf16le(src.data_ptr(), src.numel(), dst.data_ptr(),
-                                             dst.numel() if out is not None else src.numel(),
-                                             stream_handle(stream)))
+        r = _res(fn(src.data_ptr(), src.numel(), dst.data_ptr(),
+                    dst.numel() if out is not None else src.numel(), stream_handle(stream)))
     if out is not None:
         return out, r
     return dst[: r.count] if r.error == OK else dst[:0], r
@@ -187,15 +195,17 @@ def utf8_length_from_utf16le(src: torch.Tensor, stream=None) -> Result:
         return _res(lib.utf8_length_from_utf16le(src.data_ptr(), src.numel(), stream_handle(stream)))
 
 
-def convert_utf16le_to_utf8(src: torch.Tensor, out: torch.Tensor | None = None, stream=None):
-    """Returns (uint8 tensor holding the UTF-8 bytes, Result)."""
+def convert_utf16le_to_utf8(src: torch.Tensor, out: torch.Tensor | None = None, stream=None,
+                            validate: bool = True):
+    """Returns (uint8 tensor holding the UTF-8 bytes, Result).
+    validate=False: the non-validating call, for input known to be valid."""
     _check(src, _U16, "src")
+    fn = lib.convert_utf16le_to_utf8 if validate else lib.convert_valid_utf16le_to_utf8
     with torch.cuda.device(src.device):
         dst = out if out is not None else torch.empty(max(3 * src.numel(), 1), dtype=torch.uint8, device=src.device)
         _check(dst, _U8, "out")
-        r = _res(lib.convert_utf16le_to_utf8(src.data_ptr(), src.numel(), dst.data_ptr(),
-                                             dst.numel() if out is not None else 3 * src.numel(),
-                                             stream_handle(stream)))
+        r = _res(fn(src.data_ptr(), src.numel(), dst.data_ptr(),
+                    dst.numel() if out is not None else 3 * src.numel(), stream_handle(stream)))
     if out is not None:
         return out, r
     return dst[: r.count] if r.error == OK else dst[:0], r

@@ -21,7 +21,8 @@ constexpr int kChunk = 16;        // bytes per thread per sub-tile (one dwordx4)
 constexpr int kSub = kBlock * kChunk;    // sub-tile bytes (one coalesced load per thread)
 constexpr int kNoFlag = 0x7FFFFFFF;
 
-enum Mode { kValidate = 0, kLength = 1, kConvert = 2 };
+// kTrusted: convert input known to be valid (no validation; see the header)
+enum Mode { kValidate = 0, kLength = 1, kConvert = 2, kTrusted = 3 };
 
 // ---------------------------------------------------------------- workspace
 // A workspace is a WsHeader followed by one 64-bit status word per tile.

@@ -282,6 +282,32 @@ __device__ __forceinline__ void analyze_tile(const TileRegs<U> &t, const unsigne
     }
 }
 
+// Counts only, for input known to be valid: no validation, no flag. Edge
+// tiles corrected as in analyze_tile.
+template <class Dir, int U>
+__device__ __forceinline__ void count_tile(const TileRegs<U> &t, const Doc &d, unsigned long long tile,
+                                           unsigned int c[U])
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        unsigned int x[6];
+        t.chunk(u, x);
+        c[u] = Dir::count_only(x);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!tile_is_interior<U>(d, tile)) {
+        const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+        const unsigned int tid = opaque(threadIdx.x);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)tid * kChunk;
+            unsigned int lo, hi;
+            chunk_range<Dir>(d, cv, lo, hi);
+            c[u] -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
+        }
+    }
+}
+
 // Validation (and counting) of a staged tile for the validate / length
 // kernels: one sub-tile at a time in a rolled loop (the convert kernel keeps
 // the per-sub-tile counts and unrolls; here only their sum matters, and a
@@ -509,8 +535,11 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 
     unsigned long long my_flag = ~0ull;
     unsigned int c[U];
-    analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag);
-    const unsigned long long tile_flag = block_min_u64(my_flag, s.red);
+    if (MODE == kTrusted)
+        count_tile<Dir, U>(t, d, tile, c);
+    else
+        analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag);
+    const unsigned long long tile_flag = MODE == kTrusted ? ~0ull : block_min_u64(my_flag, s.red);
     unsigned int excl[U], tot[U];
     block_scan_multi<U>(c, excl, tot, s.scan);
     unsigned int agg = 0;
@@ -539,7 +568,18 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
         fin(pos + agg);
     // A tile with a flagged position makes the call fail, and the output of a
     // failed call is unspecified: only flag-free (valid) tiles are decoded.
-    if (MODE == kConvert && tile_flag == ~0ull) {
+    // Unvalidated input (kTrusted) is decoded as it is, as long as every
+    // sub-tile's count leaves room in the staging buffer for the alignment
+    // shift and the zeros past the input's end (always so for valid input;
+    // invalid input can count more, and then its tile is not decoded).
+    bool decode = MODE == kConvert && tile_flag == ~0ull;
+    if (MODE == kTrusted) {
+        decode = true;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            decode = decode && tot[u] + 2 * kChunk <= Dir::kStageUnits;
+    }
+    if (decode) {
         Out *dst = reinterpret_cast<Out *>(d.dst);
         emit_tile<Dir, U>(t, s.out + kStageFront, d, tile, excl, tot, pos, dst);
     }
@@ -554,7 +594,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 // last tile writes the call's result once its look-back is complete (every
 // tile publishes its status only after its error report has landed, so by
 // then all reports are in).
-template <class Dir, int U>
+template <class Dir, int U, int MODE>
 __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                              unsigned long long *status, unsigned long long status_cap, hu_result *out)
 {
@@ -573,27 +613,28 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
     const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang, kStatusStride};
     unsigned long long *s_wrap = &s.red[0];
-    chained_tile<Dir, U, kConvert>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
+    chained_tile<Dir, U, MODE>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
         finish_call(call, hdr, total, status, status_cap, out, s_wrap);
     });
     if (tile == n_tiles - 1)
         wrap_clear(status, status_cap, &s.red[0]);
 }
 
-template <int U>
+// MODE: kConvert, or kTrusted for input known to be valid.
+template <int U, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_convert_u8(
     Doc d, unsigned long long n_tiles, WsHeader *hdr, unsigned long long *status, unsigned long long status_cap,
     hu_result *out)
 {
-    convert_body<U8Dir, U>(d, n_tiles, hdr, status, status_cap, out);
+    convert_body<U8Dir, U, MODE>(d, n_tiles, hdr, status, status_cap, out);
 }
 
-template <int U>
+template <int U, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_convert_u16(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                                         unsigned long long *status, unsigned long long status_cap,
                                                         hu_result *out)
 {
-    convert_body<U16Dir, U>(d, n_tiles, hdr, status, status_cap, out);
+    convert_body<U16Dir, U, MODE>(d, n_tiles, hdr, status, status_cap, out);
 }
 
 }  // namespace hu

@@ -65,6 +65,9 @@ constexpr int kUConvert8 = 5;
 constexpr int kUConvert16 = 6;
 constexpr int kUScan = 8;
 
+// Internal op flag: convert without validating (input known to be valid).
+constexpr int kTrustedOp = 0x100;
+
 struct KernelChoice {
     const void *fn;
     unsigned long long tile_bytes;
@@ -74,31 +77,37 @@ struct KernelChoice {
 KernelChoice choose_kernel(int op)
 {
 #define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
+    if (op == (HU_OP_CONVERT_UTF8_TO_UTF16LE | kTrustedOp))
+        return {HU_K(k_convert_u8<kUConvert8, kTrusted>), (unsigned long long)kUConvert8 * kSub, true};
+    if (op == (HU_OP_CONVERT_UTF16LE_TO_UTF8 | kTrustedOp))
+        return {HU_K(k_convert_u16<kUConvert16, kTrusted>), (unsigned long long)kUConvert16 * kSub, true};
     switch (op) {
     case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
     case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
-    case HU_OP_CONVERT_UTF8_TO_UTF16LE: return {HU_K(k_convert_u8<kUConvert8>), (unsigned long long)kUConvert8 * kSub, true};
+    case HU_OP_CONVERT_UTF8_TO_UTF16LE: return {HU_K(k_convert_u8<kUConvert8, kConvert>), (unsigned long long)kUConvert8 * kSub, true};
     case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
     case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
-    default: return {HU_K(k_convert_u16<kUConvert16>), (unsigned long long)kUConvert16 * kSub, true};
+    default: return {HU_K(k_convert_u16<kUConvert16, kConvert>), (unsigned long long)kUConvert16 * kSub, true};
     }
 #undef HU_K
 }
 
 unsigned long long tiles_for(int op, const void *src, unsigned long long n_units)
 {
-    const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
+    const bool u16 = (op & ~kTrustedOp) >= HU_OP_VALIDATE_UTF16LE;
     const unsigned long long bytes = u16 ? 2 * n_units : n_units;
     const unsigned long long off = (unsigned long long)((uintptr_t)src & 15u);
     const unsigned long long tb = choose_kernel(op).tile_bytes;
     return (off + bytes + tb - 1) / tb;
 }
 
+// op: HU_OP_*, or a convert op | kTrustedOp
 int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
             hu_result *d_result, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
-    if (op < 0 || op > HU_OP_CONVERT_UTF16LE_TO_UTF8 || d_result == nullptr || ws == nullptr ||
+    const int base_op = op & ~kTrustedOp;
+    const bool u16 = base_op >= HU_OP_VALIDATE_UTF16LE;
+    if (base_op < 0 || base_op > HU_OP_CONVERT_UTF16LE_TO_UTF8 || d_result == nullptr || ws == nullptr ||
         ((uintptr_t)ws & 255u) != 0 || n > kMaxUnits)
         return HU_ERR_INVALID_ARGUMENT;
     if (n > 0 && src == nullptr)
@@ -107,7 +116,7 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
         return HU_ERR_INVALID_ARGUMENT;
     if (u16 && ((uintptr_t)src & 1u))
         return HU_ERR_INVALID_ARGUMENT;
-    if (op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u))
+    if (base_op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u))
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned long long n_tiles = n ? tiles_for(op, src, n) : 0;
     if (ws_bytes < kHeaderBytes + 8ull * kStatusStride * n_tiles)
@@ -314,9 +323,10 @@ hu_result make_result(int error, unsigned long long count)
 hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
                    hipStream_t stream)
 {
-    const bool u16 = op >= HU_OP_VALIDATE_UTF16LE;
+    const int base_op = op & ~kTrustedOp;
+    const bool u16 = base_op >= HU_OP_VALIDATE_UTF16LE;
     if (n > kMaxUnits || (n > 0 && src == nullptr) || (cap > 0 && dst == nullptr) ||
-        (u16 && ((uintptr_t)src & 1u)) || (op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u)))
+        (u16 && ((uintptr_t)src & 1u)) || (base_op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u)))
         return make_result(HU_ERR_INVALID_ARGUMENT, 0);
     if (n == 0)
         return make_result(HU_OK, 0);
@@ -397,6 +407,20 @@ hu_result convert_utf16le_to_utf8(const uint16_t *src, size_t n_words, uint8_t *
     return run_sync(HU_OP_CONVERT_UTF16LE_TO_UTF8, src, n_words, dst, dst_cap_bytes, (hipStream_t)stream);
 }
 
+hu_result convert_valid_utf8_to_utf16le(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                         void *stream)
+{
+    return run_sync(HU_OP_CONVERT_UTF8_TO_UTF16LE | hu::kTrustedOp, src, n_bytes, dst, dst_cap_words,
+                    (hipStream_t)stream);
+}
+
+hu_result convert_valid_utf16le_to_utf8(const uint16_t *src, size_t n_words, uint8_t *dst, size_t dst_cap_bytes,
+                                         void *stream)
+{
+    return run_sync(HU_OP_CONVERT_UTF16LE_TO_UTF8 | hu::kTrustedOp, src, n_words, dst, dst_cap_bytes,
+                    (hipStream_t)stream);
+}
+
 size_t hu_workspace_bytes(int op, size_t n_units)
 {
     if (op < 0 || op > HU_OP_CONVERT_UTF16LE_TO_UTF8)
@@ -456,6 +480,20 @@ int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *
 {
     return hu::enqueue(HU_OP_CONVERT_UTF16LE_TO_UTF8, src, n_words, dst, dst_cap_bytes, d_result, ws, ws_bytes,
                        (hipStream_t)stream);
+}
+
+int convert_valid_utf8_to_utf16le_async(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                        hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_CONVERT_UTF8_TO_UTF16LE | hu::kTrustedOp, src, n_bytes, dst, dst_cap_words, d_result,
+                       ws, ws_bytes, (hipStream_t)stream);
+}
+
+int convert_valid_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst, size_t dst_cap_bytes,
+                                        hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_CONVERT_UTF16LE_TO_UTF8 | hu::kTrustedOp, src, n_words, dst, dst_cap_bytes, d_result,
+                       ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t hu_batch_workspace_bytes(uint32_t n_docs, uint64_t total_input_bytes)

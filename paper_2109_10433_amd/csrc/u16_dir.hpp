@@ -51,6 +51,17 @@ struct U16Dir {
     // x[0..5] as for UTF-8 input (8 words per chunk, words outside the input
     // read as zero). Positions in the flag are in words relative to the chunk
     // start. Called by whole waves (the surrogate test below is a wave vote).
+    // UTF-8 bytes of the chunk's words, without any validation (a high
+    // surrogate four, a low one none).
+    __device__ __forceinline__ static unsigned int count_only(const unsigned int x[6])
+    {
+        unsigned int n = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            n += utf8_bytes_of(word(x, j));
+        return n;
+    }
+
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char * /*table*/,
                                                            int *flag)

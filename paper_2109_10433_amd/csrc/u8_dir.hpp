@@ -147,6 +147,18 @@ struct U8Dir {
     // sets *flag to the first flagged position relative to the chunk start
     // (kNoFlag if none). Truncation at the input's end is end_truncation's.
     // Called by whole waves (the narrow test below is a wave vote).
+    // UTF-16 words of the characters that start in the chunk, without any
+    // validation (words per lead as in the paper's non-validating transcoder:
+    // one, two for a lead F0..FF).
+    __device__ __forceinline__ static unsigned int count_only(const unsigned int x[6])
+    {
+        unsigned int n = 0;
+#pragma unroll
+        for (int k = 1; k <= 4; ++k)
+            n += __popc(not_cont(x[k])) + __popc(ge_e0(x[k]) & (x[k] << 3));
+        return n;
+    }
+
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char *table,
                                                            int *flag)

@@ -411,7 +411,9 @@ def main() -> int:
     ap.add_argument("--size-mib", type=int, default=256, help="UTF-8 bytes per profile (MiB)")
     ap.add_argument("--profiles", default="latin,cyrillic,cjk,emoji")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="comma list of ops to run (default all): u8u16,u16u8,len8,len16,val8,val16")
+    ap.add_argument("--only", default="", help="comma list of ops to run (default all): "
+                    "u8u16,u16u8,len8,len16,val8,val16,nv8u16,nv16u8,u8u16be,u16beu8 "
+                    "(nv: non-validating conversions; be: UTF-16 big endian)")
     ap.add_argument("--no-batched", action="store_true", help="skip the two batched document workloads")
     ap.add_argument("--docs8", type=int, default=100_000, help="UTF-8 documents in the batched workload")
     ap.add_argument("--docs16", type=int, default=10_000, help="UTF-16LE documents in the batched workload")
@@ -442,7 +444,7 @@ def main() -> int:
     sh = hu.stream_handle(stream)
     profiles = [p for p in args.profiles.split(",") if p]
     n_bytes = args.size_mib * wl.MIB
-    ops_all = ["u8u16", "u16u8", "len8", "len16", "val8", "val16"]
+    ops_all = ["u8u16", "u16u8", "len8", "len16", "val8", "val16", "nv8u16", "nv16u8", "u8u16be", "u16beu8"]
     ops = [o for o in (args.only.split(",") if args.only else ops_all) if o]
 
     # ---------------------------------------------------------------- inputs
@@ -456,6 +458,11 @@ def main() -> int:
         data[p] = dict(text=t, src8=src8, src16=src16, n8=n8, n16=n16,
                        dst16=torch.empty(n8, dtype=torch.int16, device=dev),
                        dst8=torch.empty(n8 + 64, dtype=torch.uint8, device=dev))
+        if {"u8u16be", "u16beu8"} & set(ops):
+            # the same text in UTF-16BE: each word's two bytes swapped
+            data[p]["src16be"] = src16.view(torch.uint8).view(-1, 2).flip(1).contiguous().view(torch.int16).view(-1)
+            data[p]["dst16be"] = torch.empty(n8, dtype=torch.int16, device=dev)
+            data[p]["dst8be"] = torch.empty(n8 + 64, dtype=torch.uint8, device=dev)
         log(f"{p}: {n8} B UTF-8, {n16} words UTF-16")
     log(f"inputs generated and uploaded in {time.time() - t_gen:.1f}s")
 
@@ -474,8 +481,20 @@ def main() -> int:
             "u8u16": (lambda rec, d=d: hu.lib.convert_utf8_to_utf16le_async(
                 d["src8"].data_ptr(), d["n8"], d["dst16"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
                 n8 + 2 * n16, (0, n16)),
+            "nv8u16": (lambda rec, d=d: hu.lib.convert_valid_utf8_to_utf16le_async(
+                d["src8"].data_ptr(), d["n8"], d["dst16"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
+                n8 + 2 * n16, (0, n16)),
+            "nv16u8": (lambda rec, d=d: hu.lib.convert_valid_utf16le_to_utf8_async(
+                d["src16"].data_ptr(), d["n16"], d["dst8"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
+                2 * n16 + n8, (0, n8)),
             "u16u8": (lambda rec, d=d: hu.lib.convert_utf16le_to_utf8_async(
                 d["src16"].data_ptr(), d["n16"], d["dst8"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
+                2 * n16 + n8, (0, n8)),
+            "u8u16be": (lambda rec, d=d: hu.lib.convert_utf8_to_utf16be_async(
+                d["src8"].data_ptr(), d["n8"], d["dst16be"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
+                n8 + 2 * n16, (0, n16)),
+            "u16beu8": (lambda rec, d=d: hu.lib.convert_utf16be_to_utf8_async(
+                d["src16be"].data_ptr(), d["n16"], d["dst8be"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
                 2 * n16 + n8, (0, n8)),
             "len8": (lambda rec, d=d: hu.lib.utf16_length_from_utf8_async(
                 d["src8"].data_ptr(), d["n8"], rec, w8p, w8b, sh), n8, (0, n16)),
@@ -528,6 +547,10 @@ def main() -> int:
             raise RuntimeError(f"{p}: UTF-16 output differs from the reference encoding")
         if "u16u8" in ops and not torch.equal(d["dst8"][:d["n8"]], d["src8"]):
             raise RuntimeError(f"{p}: UTF-8 output differs from the reference encoding")
+        if "u8u16be" in ops and not torch.equal(d["dst16be"][:d["n16"]], d["src16be"]):
+            raise RuntimeError(f"{p}: UTF-16BE output differs from the reference encoding")
+        if "u16beu8" in ops and not torch.equal(d["dst8be"][:d["n8"]], d["src8"]):
+            raise RuntimeError(f"{p}: UTF-8 output of the UTF-16BE input differs from the reference encoding")
 
     # ---------------------------------------------------------------- timings
     per = {}
@@ -552,6 +575,19 @@ def main() -> int:
         }
     for op in ops:
         detail[op]["aggregate_GBps"] = round(agg(op), 1)
+    # share of the validating conversion's time that validation costs (the
+    # non-validating call of the same direction beside it)
+    validation_cost = {}
+    for full, nv, name in (("u8u16", "nv8u16", "utf8_to_utf16le"), ("u16u8", "nv16u8", "utf16le_to_utf8")):
+        if full in ops and nv in ops:
+            validation_cost[name] = {p: round(1 - per[(nv, p)]["mean_s"] / per[(full, p)]["mean_s"], 3)
+                                     for p in profiles}
+    # extra time of the big-endian conversions over the little-endian ones
+    big_endian_overhead = {}
+    for le, be, name in (("u8u16", "u8u16be", "utf8_to_utf16be"), ("u16u8", "u16beu8", "utf16be_to_utf8")):
+        if le in ops and be in ops:
+            big_endian_overhead[name] = {p: round(per[(be, p)]["mean_s"] / per[(le, p)]["mean_s"] - 1, 3)
+                                         for p in profiles}
 
     headline_op = "u8u16" if "u8u16" in ops else ops[0]
     value = agg(headline_op)
@@ -656,6 +692,8 @@ def main() -> int:
         "serving": serving,
         "size_sweep": sweep,
         "detail": detail,
+        "validation_cost": validation_cost or None,
+        "big_endian_overhead": big_endian_overhead or None,
         "kernel_sources": kernel_source_digest(),
     }
     print(json.dumps(out), flush=True)

@@ -124,6 +124,33 @@ hu_result convert_valid_utf8_to_utf16le(const uint8_t *src, size_t n_bytes,
 hu_result convert_valid_utf16le_to_utf8(const uint16_t *src, size_t n_words,
                                         uint8_t *dst, size_t dst_cap_bytes, void *stream);
 
+/* UTF-16 big endian (section 3: UTF-16's two byte orders; the experiments
+ * section notes that the big-endian format costs a little-endian transcoder
+ * only a byte swap per word): the same four operations with every UTF-16 word
+ * read from, or written to, memory most significant byte first. Results,
+ * error kinds and positions (2 x word index for UTF-16 input) as for the
+ * little-endian calls; workspace as for the matching HU_OP_* little-endian
+ * op. */
+hu_result validate_utf16be(const uint16_t *src, size_t n_words, void *stream);
+hu_result utf8_length_from_utf16be(const uint16_t *src, size_t n_words, void *stream);
+hu_result convert_utf16be_to_utf8(const uint16_t *src, size_t n_words,
+                                  uint8_t *dst, size_t dst_cap_bytes, void *stream);
+hu_result convert_utf8_to_utf16be(const uint8_t *src, size_t n_bytes,
+                                  uint16_t *dst, size_t dst_cap_words, void *stream);
+
+/* Byte-order mark at the start of a buffer: UTF-16LE FF FE and UTF-16BE
+ * FE FF (section 3), UTF-8 EF BB BF (RFC 3629, section 6); checked in the
+ * order UTF-8, UTF-16LE, UTF-16BE. `head` is HOST memory holding the
+ * first n_bytes (up to 3 are read); returns the encoding and the BOM's
+ * length in bytes (HU_BOM_NONE, 0 when there is none or head is NULL). The
+ * caller skips the BOM and picks the calls for that encoding. */
+enum { HU_BOM_NONE = 0, HU_BOM_UTF8 = 1, HU_BOM_UTF16LE = 2, HU_BOM_UTF16BE = 3 };
+typedef struct {
+    int32_t encoding;   /* HU_BOM_* */
+    int32_t length;     /* bytes */
+} hu_bom;
+hu_bom hu_detect_bom(const uint8_t *head, size_t n_bytes);
+
 /* ------------------------------------------------------------------------
  * Asynchronous calls (allocate nothing, never synchronise, safe to record
  * into a HIP graph). Same operations as above; the result is written to the
@@ -165,6 +192,16 @@ int utf8_length_from_utf16le_async(const uint16_t *src, size_t n_words, hu_resul
                                    void *ws, size_t ws_bytes, void *stream);
 int convert_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst,
                                   size_t dst_cap_bytes, hu_result *d_result,
+                                  void *ws, size_t ws_bytes, void *stream);
+int validate_utf16be_async(const uint16_t *src, size_t n_words, hu_result *d_result,
+                           void *ws, size_t ws_bytes, void *stream);
+int utf8_length_from_utf16be_async(const uint16_t *src, size_t n_words, hu_result *d_result,
+                                   void *ws, size_t ws_bytes, void *stream);
+int convert_utf16be_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst,
+                                  size_t dst_cap_bytes, hu_result *d_result,
+                                  void *ws, size_t ws_bytes, void *stream);
+int convert_utf8_to_utf16be_async(const uint8_t *src, size_t n_bytes, uint16_t *dst,
+                                  size_t dst_cap_words, hu_result *d_result,
                                   void *ws, size_t ws_bytes, void *stream);
 int convert_valid_utf8_to_utf16le_async(const uint8_t *src, size_t n_bytes, uint16_t *dst,
                                         size_t dst_cap_words, hu_result *d_result,

@@ -57,6 +57,10 @@ for _name, _args in [
     ("convert_utf16le_to_utf8", [_p, _sz, _p, _sz, _p]),
     ("convert_valid_utf8_to_utf16le", [_p, _sz, _p, _sz, _p]),
     ("convert_valid_utf16le_to_utf8", [_p, _sz, _p, _sz, _p]),
+    ("validate_utf16be", [_p, _sz, _p]),
+    ("utf8_length_from_utf16be", [_p, _sz, _p]),
+    ("convert_utf16be_to_utf8", [_p, _sz, _p, _sz, _p]),
+    ("convert_utf8_to_utf16be", [_p, _sz, _p, _sz, _p]),
 ]:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = HuResult
@@ -69,9 +73,20 @@ for _name, _args in [
     ("convert_utf16le_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
     ("convert_valid_utf8_to_utf16le_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
     ("convert_valid_utf16le_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+    ("validate_utf16be_async", [_p, _sz, _p, _p, _sz, _p]),
+    ("utf8_length_from_utf16be_async", [_p, _sz, _p, _p, _sz, _p]),
+    ("convert_utf16be_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+    ("convert_utf8_to_utf16be_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
 ]:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _i
+class HuBom(ctypes.Structure):
+    _fields_ = [("encoding", ctypes.c_int32), ("length", ctypes.c_int32)]
+
+
+BOM_NONE, BOM_UTF8, BOM_UTF16LE, BOM_UTF16BE = 0, 1, 2, 3
+lib.hu_detect_bom.argtypes = [_p, _sz]
+lib.hu_detect_bom.restype = HuBom
 lib.hu_workspace_bytes.argtypes = [_i, _sz]
 lib.hu_workspace_bytes.restype = _sz
 lib.hu_workspace_init.argtypes = [_p, _sz, _p]
@@ -123,8 +138,18 @@ EXPORTED = EXPORTED_BATCH + EXPORTED_SERVER + [
     "validate_utf16le_async", "utf8_length_from_utf16le_async", "convert_utf16le_to_utf8_async",
     "convert_valid_utf8_to_utf16le", "convert_valid_utf16le_to_utf8",
     "convert_valid_utf8_to_utf16le_async", "convert_valid_utf16le_to_utf8_async",
+    "validate_utf16be", "utf8_length_from_utf16be", "convert_utf16be_to_utf8", "convert_utf8_to_utf16be",
+    "validate_utf16be_async", "utf8_length_from_utf16be_async", "convert_utf16be_to_utf8_async",
+    "convert_utf8_to_utf16be_async", "hu_detect_bom",
     "hu_workspace_bytes", "hu_workspace_init", "hu_error_name", "hu_shutdown",
 ]
+
+
+def detect_bom(head: bytes) -> tuple[int, int]:
+    """(BOM_* encoding, BOM length in bytes) of a host buffer's first bytes."""
+    buf = ctypes.create_string_buffer(bytes(head[:4]), max(len(head[:4]), 1))
+    b = lib.hu_detect_bom(ctypes.cast(buf, ctypes.c_void_p), len(head[:4]))
+    return int(b.encoding), int(b.length)
 
 
 def error_name(code: int) -> str:

@@ -149,6 +149,16 @@ __device__ __forceinline__ unsigned int opaque(unsigned int v)
     return v;
 }
 
+// Both bytes of every 16-bit word swapped (UTF-16 big endian <-> little endian).
+__device__ __forceinline__ unsigned int swap16(unsigned int v)
+{
+    return __builtin_amdgcn_perm(v, v, 0x02030001u);
+}
+__device__ __forceinline__ uint4 swap16(uint4 v)
+{
+    return make_uint4(swap16(v.x), swap16(v.y), swap16(v.z), swap16(v.w));
+}
+
 // ---------------------------------------------------------------- lanes
 // Lane l receives lane l - 1's value (DPP wave shift; lane 0 receives 0).
 __device__ __forceinline__ unsigned int from_lower_lane(unsigned int v)

@@ -97,7 +97,8 @@ __device__ __forceinline__ void load_tile(const Doc &d, unsigned long long tile,
 
 // Registers -> LDS: [16 bytes before | tile | 16 bytes after], with the bytes
 // outside the document zeroed (tiles that cover the document edges only).
-template <int U>
+// SWAP: big-endian UTF-16 input, brought to little endian here.
+template <int U, bool SWAP = false>
 __device__ __forceinline__ void stage_tile(unsigned int *in, const Doc &d, unsigned long long tile, uint4 q[U],
                                            uint4 pre, uint4 post)
 {
@@ -109,12 +110,12 @@ __device__ __forceinline__ void stage_tile(unsigned int *in, const Doc &d, unsig
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        *reinterpret_cast<uint4 *>(&in[4 + u * kSubWords + 4 * threadIdx.x]) = q[u];
+        *reinterpret_cast<uint4 *>(&in[4 + u * kSubWords + 4 * threadIdx.x]) = SWAP ? swap16(q[u]) : q[u];
     if (threadIdx.x == 0) {
         pre = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b) : make_uint4(0, 0, 0, 0);
         post = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
-        *reinterpret_cast<uint4 *>(&in[0]) = pre;
-        *reinterpret_cast<uint4 *>(&in[4 + U * kSubWords]) = post;
+        *reinterpret_cast<uint4 *>(&in[0]) = SWAP ? swap16(pre) : pre;
+        *reinterpret_cast<uint4 *>(&in[4 + U * kSubWords]) = SWAP ? swap16(post) : post;
     }
 }
 
@@ -161,8 +162,9 @@ struct TileRegs {
 
 // After load_tile: zero the bytes outside the document (tiles at its edges
 // only) and post the boundary dwords to LDS. A barrier must follow before
-// the first TileRegs::chunk.
-template <int U>
+// the first TileRegs::chunk. SWAP: big-endian UTF-16 input, brought to
+// little endian here.
+template <int U, bool SWAP = false>
 __device__ __forceinline__ void settle_tile(TileEdges<U> &e, const Doc &d, unsigned long long tile, TileRegs<U> &t,
                                             uint4 pre, uint4 post)
 {
@@ -171,6 +173,11 @@ __device__ __forceinline__ void settle_tile(TileEdges<U> &e, const Doc &d, unsig
 #pragma unroll
         for (int u = 0; u < U; ++u)
             t.q[u] = mask_granule(t.q[u], tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
+    }
+    if (SWAP) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            t.q[u] = swap16(t.q[u]);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -181,8 +188,10 @@ __device__ __forceinline__ void settle_tile(TileEdges<U> &e, const Doc &d, unsig
             e.last[u][wave] = t.q[u].w;
     }
     if (threadIdx.x == 0) {
-        e.pre = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b).w : 0u;
-        e.post = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b).x;
+        const unsigned int pw = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b).w : 0u;
+        const unsigned int px = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b).x;
+        e.pre = SWAP ? swap16(pw) : pw;
+        e.post = SWAP ? swap16(px) : px;
     }
 }
 
@@ -396,8 +405,9 @@ __device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsign
 
 // Copy staged output units out[0, shift + w) (valid from index `shift`) to
 // global units [gbase + shift, gbase + shift + w), where unit gbase sits at a
-// 16-byte aligned address; nothing at or past `cap` is written.
-template <class Dir>
+// 16-byte aligned address; nothing at or past `cap` is written. SWAP: 16-bit
+// units leave big endian.
+template <class Dir, bool SWAP = false>
 __device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned int shift, unsigned int w,
                                          typename Dir::Out *dst, long long gbase, unsigned long long cap)
 {
@@ -412,14 +422,14 @@ __device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned 
         const long long j0 = gbase + (long long)i0;
         if (i0 >= shift && i0 + G <= span && j0 >= 0 && (unsigned long long)j0 + G <= cap) {
             const uint4 v = *reinterpret_cast<const uint4 *>(out + i0);
-            *reinterpret_cast<uint4 *>(dst + j0) = v;
+            *reinterpret_cast<uint4 *>(dst + j0) = SWAP ? swap16(v) : v;
         } else {
 #pragma unroll
             for (unsigned int k = 0; k < G; ++k) {
                 const unsigned int i = i0 + k;
                 const long long j = j0 + (long long)k;
                 if (i >= shift && i < span && j >= 0 && (unsigned long long)j < cap)
-                    dst[j] = out[i];
+                    dst[j] = SWAP ? (Out)((out[i] >> 8) | (out[i] << 8)) : out[i];
             }
         }
     }
@@ -444,7 +454,7 @@ __device__ __forceinline__ void workgroup_exit(unsigned long long my_total, unsi
 }
 
 // ------------------------------------------------------------ validate / length
-template <class Dir, int MODE, int U>
+template <class Dir, int MODE, int U, bool SWAP = false>
 __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                                  unsigned long long *status, unsigned long long status_cap,
                                                  hu_result *out)
@@ -458,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
     if (tile < n_tiles)
         load_tile<U>(d, tile, q, pre, post);
     while (tile < n_tiles) {
-        stage_tile<U>(s.in, d, tile, q, pre, post);
+        stage_tile<U, SWAP>(s.in, d, tile, q, pre, post);
         __syncthreads();
         const unsigned long long next = tile + gridDim.x;
         if (next < n_tiles)
@@ -480,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
 // those before its start (only in the first chunk of the first tile, fewer
 // than 16 bytes of alignment) land just before the chunk's output, in the
 // staging buffer's front margin.
-template <class Dir, int U>
+template <class Dir, int U, bool SWAP = false>
 __device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Out *stage, const Doc &d,
                                           unsigned long long tile, const unsigned int excl[U], const unsigned int tot[U],
                                           unsigned long long pos, typename Dir::Out *dst)
@@ -498,7 +508,7 @@ __device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Ou
         Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u));
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
-        copy_out<Dir>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
+        copy_out<Dir, SWAP>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
         __syncthreads();
         pos += tot[u];
     }
@@ -520,7 +530,8 @@ struct Chain {
 // publish, look back; thread 0 of the document's last tile then calls
 // fin(total output units); in convert mode the tile's output is written.
 // The pair table must already be in s.table. All threads must call.
-template <class Dir, int U, int MODE, class Finisher>
+// SWAP_IN: big-endian UTF-16 input; SWAP_OUT: big-endian UTF-16 output.
+template <class Dir, int U, int MODE, bool SWAP_IN = false, bool SWAP_OUT = false, class Finisher>
 __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc &d, unsigned long long tile,
                                              unsigned long long n_tiles, const Chain &cx, Finisher fin)
 {
@@ -530,7 +541,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     t.e = &s.edges;
     uint4 pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
     load_tile<U>(d, tile, t.q, pre, post);
-    settle_tile<U>(s.edges, d, tile, t, pre, post);
+    settle_tile<U, SWAP_IN>(s.edges, d, tile, t, pre, post);
     __syncthreads();
 
     unsigned long long my_flag = ~0ull;
@@ -581,7 +592,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     }
     if (decode) {
         Out *dst = reinterpret_cast<Out *>(d.dst);
-        emit_tile<Dir, U>(t, s.out + kStageFront, d, tile, excl, tot, pos, dst);
+        emit_tile<Dir, U, SWAP_OUT>(t, s.out + kStageFront, d, tile, excl, tot, pos, dst);
     }
 }
 
@@ -594,7 +605,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 // last tile writes the call's result once its look-back is complete (every
 // tile publishes its status only after its error report has landed, so by
 // then all reports are in).
-template <class Dir, int U, int MODE>
+template <class Dir, int U, int MODE, bool SWAP_IN, bool SWAP_OUT>
 __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                              unsigned long long *status, unsigned long long status_cap, hu_result *out)
 {
@@ -613,28 +624,29 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
     const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang, kStatusStride};
     unsigned long long *s_wrap = &s.red[0];
-    chained_tile<Dir, U, MODE>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
+    chained_tile<Dir, U, MODE, SWAP_IN, SWAP_OUT>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
         finish_call(call, hdr, total, status, status_cap, out, s_wrap);
     });
     if (tile == n_tiles - 1)
         wrap_clear(status, status_cap, &s.red[0]);
 }
 
-// MODE: kConvert, or kTrusted for input known to be valid.
-template <int U, int MODE>
+// MODE: kConvert, or kTrusted for input known to be valid. BE: the UTF-16
+// side is big endian.
+template <int U, int MODE, bool BE = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_convert_u8(
     Doc d, unsigned long long n_tiles, WsHeader *hdr, unsigned long long *status, unsigned long long status_cap,
     hu_result *out)
 {
-    convert_body<U8Dir, U, MODE>(d, n_tiles, hdr, status, status_cap, out);
+    convert_body<U8Dir, U, MODE, false, BE>(d, n_tiles, hdr, status, status_cap, out);
 }
 
-template <int U, int MODE>
+template <int U, int MODE, bool BE = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_convert_u16(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                                         unsigned long long *status, unsigned long long status_cap,
                                                         hu_result *out)
 {
-    convert_body<U16Dir, U, MODE>(d, n_tiles, hdr, status, status_cap, out);
+    convert_body<U16Dir, U, MODE, BE, false>(d, n_tiles, hdr, status, status_cap, out);
 }
 
 }  // namespace hu

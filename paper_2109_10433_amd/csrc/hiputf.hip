@@ -65,8 +65,11 @@ constexpr int kUConvert8 = 5;
 constexpr int kUConvert16 = 6;
 constexpr int kUScan = 8;
 
-// Internal op flag: convert without validating (input known to be valid).
+// Internal op flags: convert without validating (input known to be valid);
+// the UTF-16 side is big endian.
 constexpr int kTrustedOp = 0x100;
+constexpr int kBigEndianOp = 0x200;
+constexpr int kOpFlags = kTrustedOp | kBigEndianOp;
 
 struct KernelChoice {
     const void *fn;
@@ -81,6 +84,14 @@ KernelChoice choose_kernel(int op)
         return {HU_K(k_convert_u8<kUConvert8, kTrusted>), (unsigned long long)kUConvert8 * kSub, true};
     if (op == (HU_OP_CONVERT_UTF16LE_TO_UTF8 | kTrustedOp))
         return {HU_K(k_convert_u16<kUConvert16, kTrusted>), (unsigned long long)kUConvert16 * kSub, true};
+    if (op == (HU_OP_CONVERT_UTF8_TO_UTF16LE | kBigEndianOp))
+        return {HU_K(k_convert_u8<kUConvert8, kConvert, true>), (unsigned long long)kUConvert8 * kSub, true};
+    if (op == (HU_OP_CONVERT_UTF16LE_TO_UTF8 | kBigEndianOp))
+        return {HU_K(k_convert_u16<kUConvert16, kConvert, true>), (unsigned long long)kUConvert16 * kSub, true};
+    if (op == (HU_OP_VALIDATE_UTF16LE | kBigEndianOp))
+        return {HU_K(k_scan<U16Dir, kValidate, kUScan, true>), (unsigned long long)kUScan * kSub, false};
+    if (op == (HU_OP_UTF8_LENGTH_FROM_UTF16LE | kBigEndianOp))
+        return {HU_K(k_scan<U16Dir, kLength, kUScan, true>), (unsigned long long)kUScan * kSub, false};
     switch (op) {
     case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
     case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
@@ -94,18 +105,18 @@ KernelChoice choose_kernel(int op)
 
 unsigned long long tiles_for(int op, const void *src, unsigned long long n_units)
 {
-    const bool u16 = (op & ~kTrustedOp) >= HU_OP_VALIDATE_UTF16LE;
+    const bool u16 = (op & ~kOpFlags) >= HU_OP_VALIDATE_UTF16LE;
     const unsigned long long bytes = u16 ? 2 * n_units : n_units;
     const unsigned long long off = (unsigned long long)((uintptr_t)src & 15u);
     const unsigned long long tb = choose_kernel(op).tile_bytes;
     return (off + bytes + tb - 1) / tb;
 }
 
-// op: HU_OP_*, or a convert op | kTrustedOp
+// op: HU_OP_* with the flags above (only on the combinations choose_kernel has)
 int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
             hu_result *d_result, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    const int base_op = op & ~kTrustedOp;
+    const int base_op = op & ~kOpFlags;
     const bool u16 = base_op >= HU_OP_VALIDATE_UTF16LE;
     if (base_op < 0 || base_op > HU_OP_CONVERT_UTF16LE_TO_UTF8 || d_result == nullptr || ws == nullptr ||
         ((uintptr_t)ws & 255u) != 0 || n > kMaxUnits)
@@ -323,7 +334,7 @@ hu_result make_result(int error, unsigned long long count)
 hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, unsigned long long cap,
                    hipStream_t stream)
 {
-    const int base_op = op & ~kTrustedOp;
+    const int base_op = op & ~kOpFlags;
     const bool u16 = base_op >= HU_OP_VALIDATE_UTF16LE;
     if (n > kMaxUnits || (n > 0 && src == nullptr) || (cap > 0 && dst == nullptr) ||
         (u16 && ((uintptr_t)src & 1u)) || (base_op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u)))
@@ -421,6 +432,45 @@ hu_result convert_valid_utf16le_to_utf8(const uint16_t *src, size_t n_words, uin
                     (hipStream_t)stream);
 }
 
+hu_result validate_utf16be(const uint16_t *src, size_t n_words, void *stream)
+{
+    return run_sync(HU_OP_VALIDATE_UTF16LE | hu::kBigEndianOp, src, n_words, nullptr, 0, (hipStream_t)stream);
+}
+
+hu_result utf8_length_from_utf16be(const uint16_t *src, size_t n_words, void *stream)
+{
+    return run_sync(HU_OP_UTF8_LENGTH_FROM_UTF16LE | hu::kBigEndianOp, src, n_words, nullptr, 0,
+                    (hipStream_t)stream);
+}
+
+hu_result convert_utf16be_to_utf8(const uint16_t *src, size_t n_words, uint8_t *dst, size_t dst_cap_bytes,
+                                  void *stream)
+{
+    return run_sync(HU_OP_CONVERT_UTF16LE_TO_UTF8 | hu::kBigEndianOp, src, n_words, dst, dst_cap_bytes,
+                    (hipStream_t)stream);
+}
+
+hu_result convert_utf8_to_utf16be(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                  void *stream)
+{
+    return run_sync(HU_OP_CONVERT_UTF8_TO_UTF16LE | hu::kBigEndianOp, src, n_bytes, dst, dst_cap_words,
+                    (hipStream_t)stream);
+}
+
+hu_bom hu_detect_bom(const uint8_t *head, size_t n_bytes)
+{
+    hu_bom b{HU_BOM_NONE, 0};
+    if (head == nullptr)
+        return b;
+    if (n_bytes >= 3 && head[0] == 0xEF && head[1] == 0xBB && head[2] == 0xBF)
+        b = {HU_BOM_UTF8, 3};
+    else if (n_bytes >= 2 && head[0] == 0xFF && head[1] == 0xFE)
+        b = {HU_BOM_UTF16LE, 2};
+    else if (n_bytes >= 2 && head[0] == 0xFE && head[1] == 0xFF)
+        b = {HU_BOM_UTF16BE, 2};
+    return b;
+}
+
 size_t hu_workspace_bytes(int op, size_t n_units)
 {
     if (op < 0 || op > HU_OP_CONVERT_UTF16LE_TO_UTF8)
@@ -493,6 +543,34 @@ int convert_valid_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uin
                                         hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
 {
     return hu::enqueue(HU_OP_CONVERT_UTF16LE_TO_UTF8 | hu::kTrustedOp, src, n_words, dst, dst_cap_bytes, d_result,
+                       ws, ws_bytes, (hipStream_t)stream);
+}
+
+int validate_utf16be_async(const uint16_t *src, size_t n_words, hu_result *d_result, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    return hu::enqueue(HU_OP_VALIDATE_UTF16LE | hu::kBigEndianOp, src, n_words, nullptr, 0, d_result, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+int utf8_length_from_utf16be_async(const uint16_t *src, size_t n_words, hu_result *d_result, void *ws,
+                                   size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_UTF8_LENGTH_FROM_UTF16LE | hu::kBigEndianOp, src, n_words, nullptr, 0, d_result, ws,
+                       ws_bytes, (hipStream_t)stream);
+}
+
+int convert_utf16be_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst, size_t dst_cap_bytes,
+                                  hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_CONVERT_UTF16LE_TO_UTF8 | hu::kBigEndianOp, src, n_words, dst, dst_cap_bytes, d_result,
+                       ws, ws_bytes, (hipStream_t)stream);
+}
+
+int convert_utf8_to_utf16be_async(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                  hu_result *d_result, void *ws, size_t ws_bytes, void *stream)
+{
+    return hu::enqueue(HU_OP_CONVERT_UTF8_TO_UTF16LE | hu::kBigEndianOp, src, n_bytes, dst, dst_cap_words, d_result,
                        ws, ws_bytes, (hipStream_t)stream);
 }
 

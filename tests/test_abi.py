@@ -40,3 +40,25 @@ def test_binding_lists_match_header():
     from paper_2109_10433_amd import binding
     assert sorted(binding.EXPORTED) == sorted(n for n in declared_functions() if n in binding.EXPORTED)
     assert set(declared_functions()) <= set(binding.EXPORTED) | set(getattr(binding, "EXPORTED_EXTRA", []))
+
+
+def test_detect_bom_on_the_host():
+    """Byte-order marks of section 3 (UTF-16: FF FE little endian, FE FF big
+    endian) and RFC 3629's EF BB BF; a host-only call, no GPU involved."""
+    from paper_2109_10433_amd import binding as hu
+    cases = [
+        (b"\xef\xbb\xbfabc", (hu.BOM_UTF8, 3)),
+        (b"\xff\xfea\x00", (hu.BOM_UTF16LE, 2)),
+        (b"\xfe\xff\x00a", (hu.BOM_UTF16BE, 2)),
+        (b"\xef\xbb", (hu.BOM_NONE, 0)),          # truncated UTF-8 mark
+        (b"\xff", (hu.BOM_NONE, 0)),
+        (b"", (hu.BOM_NONE, 0)),
+        (b"abc", (hu.BOM_NONE, 0)),
+        (b"\xfe\xfe", (hu.BOM_NONE, 0)),
+        (b"\xef\xbb\xbe", (hu.BOM_NONE, 0)),
+        (b"\xff\xfe\x00\x00", (hu.BOM_UTF16LE, 2)),  # UTF-32LE's mark starts the same way
+    ]
+    for head, want in cases:
+        assert hu.detect_bom(head) == want, head
+    r = hu.lib.hu_detect_bom(None, 3)
+    assert (r.encoding, r.length) == (hu.BOM_NONE, 0)

@@ -1,7 +1,8 @@
 """Build the gfx950 shared library ``libhiputf.so`` in-tree: ``python -m paper_2109_10433_amd.build``.
 
-One hipcc invocation over csrc/hiputf.hip (kernels and the C ABI) and
-csrc/serve.hip (the server, host code). Packed FP32 instruction selection is
+One hipcc invocation over csrc/hiputf.hip (kernels and the C ABI),
+csrc/variants.hip (non-validating and big-endian kernels) and csrc/serve.hip
+(the server, host code). Packed FP32 instruction selection is
 disabled for all device code.
 """
 from __future__ import annotations
@@ -25,7 +26,8 @@ HIPCC_FLAGS = [
 def build(extra=(), out: str = LIB, verbose: bool = False) -> str:
     tmp = out + ".tmp"
     cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
-           os.path.join(PKG, "csrc", "hiputf.hip"), os.path.join(PKG, "csrc", "serve.hip"), "-o", tmp]
+           os.path.join(PKG, "csrc", "hiputf.hip"), os.path.join(PKG, "csrc", "variants.hip"),
+           os.path.join(PKG, "csrc", "serve.hip"), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

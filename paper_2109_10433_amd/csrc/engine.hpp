@@ -108,14 +108,23 @@ __device__ __forceinline__ void stage_tile(unsigned int *in, const Doc &d, unsig
         for (int u = 0; u < U; ++u)
             q[u] = mask_granule(q[u], tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
     }
+    if constexpr (SWAP) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = swap16(q[u]);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        *reinterpret_cast<uint4 *>(&in[4 + u * kSubWords + 4 * threadIdx.x]) = SWAP ? swap16(q[u]) : q[u];
+        *reinterpret_cast<uint4 *>(&in[4 + u * kSubWords + 4 * threadIdx.x]) = q[u];
     if (threadIdx.x == 0) {
         pre = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b) : make_uint4(0, 0, 0, 0);
         post = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
-        *reinterpret_cast<uint4 *>(&in[0]) = SWAP ? swap16(pre) : pre;
-        *reinterpret_cast<uint4 *>(&in[4 + U * kSubWords]) = SWAP ? swap16(post) : post;
+        if constexpr (SWAP) {
+            pre = swap16(pre);
+            post = swap16(post);
+        }
+        *reinterpret_cast<uint4 *>(&in[0]) = pre;
+        *reinterpret_cast<uint4 *>(&in[4 + U * kSubWords]) = post;
     }
 }
 
@@ -174,7 +183,7 @@ __device__ __forceinline__ void settle_tile(TileEdges<U> &e, const Doc &d, unsig
         for (int u = 0; u < U; ++u)
             t.q[u] = mask_granule(t.q[u], tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
     }
-    if (SWAP) {
+    if constexpr (SWAP) {
 #pragma unroll
         for (int u = 0; u < U; ++u)
             t.q[u] = swap16(t.q[u]);

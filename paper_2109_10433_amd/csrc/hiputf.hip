@@ -15,6 +15,7 @@
 
 #include "batch.hpp"
 #include "hiputf.h"
+#include "kernel_choice.hpp"
 
 namespace hu {
 
@@ -57,41 +58,14 @@ int max_resident_blocks(const void *kernel)
 
 constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 bits
 
-// sub-tiles per tile (tile = U x 4 KiB of input)
-// Sub-tiles per convert tile: the largest that still fit 64 registers (eight
-// waves per SIMD); bigger tiles mean fewer look-backs per byte. UTF-8 input
-// at 6 would spill; UTF-16 input fits 6 when held to eight waves.
-constexpr int kUConvert8 = 5;
-constexpr int kUConvert16 = 6;
-constexpr int kUScan = 8;
-
-// Internal op flags: convert without validating (input known to be valid);
-// the UTF-16 side is big endian.
-constexpr int kTrustedOp = 0x100;
-constexpr int kBigEndianOp = 0x200;
-constexpr int kOpFlags = kTrustedOp | kBigEndianOp;
-
-struct KernelChoice {
-    const void *fn;
-    unsigned long long tile_bytes;
-    bool one_group_per_tile;   // else: persistent, grid-stride over tiles
-};
-
 KernelChoice choose_kernel(int op)
 {
 #define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
-    if (op == (HU_OP_CONVERT_UTF8_TO_UTF16LE | kTrustedOp))
-        return {HU_K(k_convert_u8<kUConvert8, kTrusted>), (unsigned long long)kUConvert8 * kSub, true};
-    if (op == (HU_OP_CONVERT_UTF16LE_TO_UTF8 | kTrustedOp))
-        return {HU_K(k_convert_u16<kUConvert16, kTrusted>), (unsigned long long)kUConvert16 * kSub, true};
-    if (op == (HU_OP_CONVERT_UTF8_TO_UTF16LE | kBigEndianOp))
-        return {HU_K(k_convert_u8<kUConvert8, kConvert, true>), (unsigned long long)kUConvert8 * kSub, true};
-    if (op == (HU_OP_CONVERT_UTF16LE_TO_UTF8 | kBigEndianOp))
-        return {HU_K(k_convert_u16<kUConvert16, kConvert, true>), (unsigned long long)kUConvert16 * kSub, true};
-    if (op == (HU_OP_VALIDATE_UTF16LE | kBigEndianOp))
-        return {HU_K(k_scan<U16Dir, kValidate, kUScan, true>), (unsigned long long)kUScan * kSub, false};
-    if (op == (HU_OP_UTF8_LENGTH_FROM_UTF16LE | kBigEndianOp))
-        return {HU_K(k_scan<U16Dir, kLength, kUScan, true>), (unsigned long long)kUScan * kSub, false};
+    if ((op & kOpFlags) != 0) {   // no kernel for the combination: fn stays null
+        KernelChoice kc{nullptr, (unsigned long long)kSub, true};
+        choose_variant(op, kc);
+        return kc;
+    }
     switch (op) {
     case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
     case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
@@ -128,6 +102,8 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     if (u16 && ((uintptr_t)src & 1u))
         return HU_ERR_INVALID_ARGUMENT;
     if (base_op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u))
+        return HU_ERR_INVALID_ARGUMENT;
+    if (choose_kernel(op).fn == nullptr)
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned long long n_tiles = n ? tiles_for(op, src, n) : 0;
     if (ws_bytes < kHeaderBytes + 8ull * kStatusStride * n_tiles)

@@ -48,9 +48,6 @@ struct U16Dir {
         return (x[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
     }
 
-    // x[0..5] as for UTF-8 input (8 words per chunk, words outside the input
-    // read as zero). Positions in the flag are in words relative to the chunk
-    // start. Called by whole waves (the surrogate test below is a wave vote).
     // UTF-8 bytes of the chunk's words, without any validation (a high
     // surrogate four, a low one none).
     __device__ __forceinline__ static unsigned int count_only(const unsigned int x[6])
@@ -62,6 +59,9 @@ struct U16Dir {
         return n;
     }
 
+    // x[0..5] as for UTF-8 input (8 words per chunk, words outside the input
+    // read as zero). Positions in the flag are in words relative to the chunk
+    // start. Called by whole waves (the surrogate test below is a wave vote).
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char * /*table*/,
                                                            int *flag)

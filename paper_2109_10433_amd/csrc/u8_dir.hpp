@@ -141,12 +141,6 @@ struct U8Dir {
     // byte plus one (a four-byte lead in the last byte)
     static constexpr unsigned int kStageUnits = kSub + 40;
 
-    // x[0]: the 4 bytes before the chunk, x[1..4]: the chunk, x[5]: the 4
-    // bytes after (bytes outside the input read as zero). Returns the number
-    // of UTF-16 words of the characters that start in the chunk (if COUNT) and
-    // sets *flag to the first flagged position relative to the chunk start
-    // (kNoFlag if none). Truncation at the input's end is end_truncation's.
-    // Called by whole waves (the narrow test below is a wave vote).
     // UTF-16 words of the characters that start in the chunk, without any
     // validation (words per lead as in the paper's non-validating transcoder:
     // one, two for a lead F0..FF).
@@ -159,6 +153,12 @@ struct U8Dir {
         return n;
     }
 
+    // x[0]: the 4 bytes before the chunk, x[1..4]: the chunk, x[5]: the 4
+    // bytes after (bytes outside the input read as zero). Returns the number
+    // of UTF-16 words of the characters that start in the chunk (if COUNT) and
+    // sets *flag to the first flagged position relative to the chunk start
+    // (kNoFlag if none). Truncation at the input's end is end_truncation's.
+    // Called by whole waves (the narrow test below is a wave vote).
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char *table,
                                                            int *flag)

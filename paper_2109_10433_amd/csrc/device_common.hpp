@@ -159,6 +159,22 @@ __device__ __forceinline__ uint4 swap16(uint4 v)
     return make_uint4(swap16(v.x), swap16(v.y), swap16(v.z), swap16(v.w));
 }
 
+// Two 16-bit lanes of a register, for packed 16-bit integer arithmetic.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// Byte b of the result: the number of set bytes among bytes 0..b of q, whose
+// bytes are each 0 or a small count (no byte of the result may exceed 255).
+// Two shift-adds; written out so that they do not become a (slower) full
+// 32-bit multiply by 0x01010101.
+__device__ __forceinline__ unsigned int byte_prefix_sum(unsigned int q)
+{
+    unsigned int s, r;
+    asm("v_lshl_add_u32 %0, %1, 8, %1" : "=v"(s) : "v"(q));
+    asm("v_lshl_add_u32 %0, %1, 16, %1" : "=v"(r) : "v"(s));
+    return r;
+}
+
 // ---------------------------------------------------------------- lanes
 // Lane l receives lane l - 1's value (DPP wave shift; lane 0 receives 0).
 __device__ __forceinline__ unsigned int from_lower_lane(unsigned int v)

@@ -17,8 +17,6 @@
 
 namespace hu {
 
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
 __device__ __forceinline__ bool is_high(unsigned int w) { return (w & 0xFC00u) == 0xD800u; }
 __device__ __forceinline__ bool is_low(unsigned int w) { return (w & 0xFC00u) == 0xDC00u; }
 

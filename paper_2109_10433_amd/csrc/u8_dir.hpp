@@ -305,18 +305,20 @@ struct U8Dir {
     // Decoding without a branch per character, for waves whose characters
     // have at most MAXB bytes: 2 is the first case of the paper's Algorithm
     // "core component", 3 its second (one 16-bit word per character). The
-    // word at byte position p, as if p held a lead b (bit layouts of section
-    // 3): b < 0x80: b;  C0..DF: ((b & 0x1F) << 6) | (n1 & 0x3F);  E0..EF:
-    // ((b & 0x0F) << 12) | ((n1 & 0x3F) << 6) | (n2 & 0x3F), with n1, n2 the
-    // following bytes. Words are formed two positions per register (16-bit
-    // halves) for all 16 positions, junk at continuation bytes. Every position
-    // then stores its word without a branch, positions in descending order, at
-    // the slot of the last lead at or before it: a continuation byte's junk
-    // lands in the slot of its lead (or of the character before), which that
-    // character, stored later, overwrites. The first bytes of the chunk (up to
-    // three, whatever MAXB) can precede its first lead (the rest of a
-    // character begun in the previous chunk); they store only when a lead is
-    // at or before them.
+    // word at byte position p, as if p held a lead b followed by n1, n2 (bit
+    // layouts of section 3): b < 0x80: b;  C0..DF: ((b & 0x1F) << 6) |
+    // (n1 & 0x3F);  E0..EF: ((b & 0x0F) << 12) | ((n1 & 0x3F) << 6) |
+    // (n2 & 0x3F). With n1, n2 continuation bytes (10xxxxxx) these equal
+    // (b << 6) ^ n1 ^ 0x3080 and, modulo 2^16, (b << 12) + (n1 << 6) + n2 -
+    // 0x2080, which need no masking: words are formed two positions per
+    // register (16-bit halves, packed 16-bit arithmetic for the second) for
+    // all 16 positions, junk at continuation bytes. Every position then stores
+    // its word without a branch, positions in descending order, at the slot of
+    // the last lead at or before it: a continuation byte's junk lands in the
+    // slot of its lead (or of the character before), which that character,
+    // stored later, overwrites. The first bytes of the chunk (up to three,
+    // whatever MAXB) can precede its first lead (the rest of a character begun
+    // in the previous chunk); they store only when a lead is at or before them.
     template <int MAXB>
     __device__ __forceinline__ static void emit_direct(const unsigned int x[6], const unsigned int lead[4], Out *out,
                                                        unsigned int o)
@@ -329,45 +331,57 @@ struct U8Dir {
         for (int k = 1; k < 4; ++k)
             first[k] = first[k - 1] + __popc(lead[k - 1]);
         char *base = reinterpret_cast<char *>(out);
+        // 64 in both halves, kept in a register so that the products below
+        // stay multiply-adds instead of becoming shifts and adds
+        u16x2 k64 = {64, 64};
+        if constexpr (MAXB >= 3)
+            k64 = __builtin_bit_cast(u16x2, opaque(0x00400040u));
 #pragma unroll
         for (int k = 3; k >= 0; --k) {
-            const unsigned int a = x[k + 1];
-            const unsigned int n = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 1);    // next bytes
-            const unsigned int n2 = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], 2);   // the bytes after
+            const unsigned int lo = x[k + 1], hi = x[k + 2];   // this dword and the next
+            // bytes (p, p + 1) of hi:lo into the low bytes of the two halves
+            const unsigned int a2[2] = {__builtin_amdgcn_perm(hi, lo, 0x0C010C00u),
+                                        __builtin_amdgcn_perm(hi, lo, 0x0C030C02u)};
+            const unsigned int b2[2] = {__builtin_amdgcn_perm(hi, lo, 0x0C020C01u),
+                                        __builtin_amdgcn_perm(hi, lo, 0x0C040C03u)};
+            // 0xFFFF in the halves whose byte is >= 0x80: permute selectors 8..11
+            // copy the top bit of bytes 1, 3, 5, 7 of (lo : lo << 8)
+            const unsigned int lo8 = lo << 8;
+            const unsigned int m[2] = {__builtin_amdgcn_perm(lo, lo8, 0x0A0A0808u),
+                                       __builtin_amdgcn_perm(lo, lo8, 0x0B0B0909u)};
             unsigned int W[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const unsigned int sel = h == 0 ? 0x0C010C00u : 0x0C030C02u;   // bytes 2h, 2h+1 -> halves
-                const unsigned int a2 = __builtin_amdgcn_perm(0u, a, sel);
-                const unsigned int b2 = __builtin_amdgcn_perm(0u, n, sel);
-                // bits 6..10 from the lead's low five bits, bits 0..5 from the next byte
-                const unsigned int two = (((a2 << 6) & 0x07C007C0u) | (b2 & 0x003F003Fu));
-                const unsigned int m = ((a2 >> 7) & 0x00010001u) * 0xFFFFu;   // halves with b >= 0x80
-                unsigned int w = (two & m) | (a2 & ~m);
+                // bitop3 truth tables: 0x96 a ^ b ^ c, 0xE4 (a & c) | (b & ~c)
+                const unsigned int two = __builtin_amdgcn_bitop3_b32(a2[h] << 6, b2[h], 0x30803080u, 0x96);
+                unsigned int w = __builtin_amdgcn_bitop3_b32(two, a2[h], m[h], 0xE4);
                 if (MAXB >= 3) {
-                    const unsigned int c2 = __builtin_amdgcn_perm(0u, n2, sel);
-                    const unsigned int three =
-                        ((a2 << 12) & 0xF000F000u) | ((b2 << 6) & 0x0FC00FC0u) | (c2 & 0x003F003Fu);
-                    const unsigned int m3 = ((a2 >> 5) & (a2 >> 6) & m & 0x00010001u) * 0xFFFFu;   // b >= 0xE0
-                    w = (three & m3) | (w & ~m3);
+                    const unsigned int c2 = h == 0 ? a2[1] : __builtin_amdgcn_perm(hi, lo, 0x0C050C04u);
+                    const u16x2 av = __builtin_bit_cast(u16x2, a2[h]);
+                    // (b * 64 + n1) * 64 + n2 - 0x2080 in each half (multiply-adds)
+                    u16x2 t = av * k64 + __builtin_bit_cast(u16x2, b2[h]);
+                    t = t * k64 + __builtin_bit_cast(u16x2, c2);
+                    t -= (u16x2)(0x2080);
+                    // 0xFFFF in the halves whose byte is below 0xE0
+                    const unsigned int below =
+                        __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
+                    w = __builtin_amdgcn_bitop3_b32(w, __builtin_bit_cast(unsigned int, t), below, 0xE4);
                 }
                 W[h] = w;
             }
-            // byte b of incl: leads among bytes 0..b of this dword
-            const unsigned int q = lead[k] >> 7;
-            const unsigned int s1 = q + (q << 8);
-            const unsigned int incl = s1 + (s1 << 16);
+            // byte b of incl2: twice the leads among bytes 0..b of this dword
+            const unsigned int incl2 = byte_prefix_sum(lead[k] >> 6);
             const unsigned int a0 = 2u * first[k] - 2u;   // address of slot (first - 1)
 #pragma unroll
             for (int b = 3; b >= 0; --b) {
-                const unsigned int addr = a0 + 2u * ((incl >> (8 * b)) & 0xFFu);
-                unsigned short *p = reinterpret_cast<unsigned short *>(base + addr);
+                const unsigned int ib = (incl2 >> (8 * b)) & 0xFFu;
+                unsigned short *p = reinterpret_cast<unsigned short *>(base + a0 + ib);
                 const unsigned short v = (unsigned short)((b & 1) ? (W[b >> 1] >> 16) : W[b >> 1]);
                 // chunk start: positions before the first lead store nothing
                 // (up to three: the chunk before may end with any lead, even
                 // in a wave that took another path)
                 const bool guard = k == 0 && b < 3;
-                if (!guard || ((incl >> (8 * b)) & 0xFFu) != 0)
+                if (!guard || ib != 0)
                     *p = v;
             }
         }

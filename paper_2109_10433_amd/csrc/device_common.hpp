@@ -189,14 +189,31 @@ __device__ __forceinline__ unsigned int from_upper_lane(unsigned int v)
 }
 
 // ---------------------------------------------------------------- scans
+// Inclusive prefix sum over the wave's 64 lanes with DPP moves: shifts by 1,
+// 2, 4 and 8 lanes inside each row of 16 (lanes shifted in from outside the
+// row read 0), then the last lane of row 0 and of row 2 added to rows 1 and 3
+// (row_bcast:15), and lane 31 added to rows 2 and 3 (row_bcast:31). Rows the
+// row mask leaves out keep the 0 they start from.
 __device__ __forceinline__ unsigned int wave_inclusive_sum(unsigned int v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        unsigned int u = __shfl_up(v, d, 64);
-        if (lane >= d)
-            v += u;
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
+// Minimum over the wave. Flags are rare: a wave whose lanes all hold ~0 (no
+// flag) settles it with one vote.
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
+{
+    if (__any(v != ~0ull)) {
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long u = __shfl_xor(v, off, 64);
+            v = u < v ? u : v;
+        }
     }
     return v;
 }
@@ -205,10 +222,7 @@ __device__ __forceinline__ unsigned long long block_min_u64(unsigned long long v
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    for (int off = 32; off > 0; off >>= 1) {
-        unsigned long long u = __shfl_xor(v, off, 64);
-        v = u < v ? u : v;
-    }
+    v = wave_min_u64(v);
     if (lane == 0)
         s_tmp[wave] = v;
     __syncthreads();

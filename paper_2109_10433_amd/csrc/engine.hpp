@@ -369,13 +369,21 @@ __device__ __forceinline__ void scan_tile(const unsigned int *in, const unsigned
 
 // Exclusive offsets of every thread's count for each of U sub-tiles, and the
 // sub-tile totals, with one barrier. Counts are at most 32 per thread, so two
-// sub-tiles share one 32-bit scan (a wave's total stays below 2^16).
-template <int U>
+// sub-tiles share one 32-bit scan (a wave's total stays below 2^16). With
+// FLAG, the same barrier also yields the workgroup's smallest flag.
+template <int U, bool FLAG = false>
 __device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsigned int excl[U], unsigned int tot[U],
-                                                 unsigned int (*s_scan)[kWaves])
+                                                 unsigned int (*s_scan)[kWaves], unsigned long long flag = ~0ull,
+                                                 unsigned long long *s_red = nullptr,
+                                                 unsigned long long *flag_min = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    if constexpr (FLAG) {
+        const unsigned long long m = wave_min_u64(flag);
+        if (lane == 0)
+            s_red[wave] = m;
+    }
 #pragma unroll
     for (int i = 0; i < U; i += 2) {
         if (i + 1 < U) {
@@ -409,6 +417,13 @@ __device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsign
         // done here, not sunk past the look-back with the loaded totals kept live
         asm volatile("" : "+v"(excl[u]) :: "memory");
         tot[u] = __builtin_amdgcn_readfirstlane(all);   // uniform: keep it in a scalar register
+    }
+    if constexpr (FLAG) {
+        unsigned long long m = s_red[0];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w)
+            m = s_red[w] < m ? s_red[w] : m;
+        *flag_min = m;
     }
 }
 
@@ -559,9 +574,9 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
         count_tile<Dir, U>(t, d, tile, c);
     else
         analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag);
-    const unsigned long long tile_flag = MODE == kTrusted ? ~0ull : block_min_u64(my_flag, s.red);
+    unsigned long long tile_flag = ~0ull;
     unsigned int excl[U], tot[U];
-    block_scan_multi<U>(c, excl, tot, s.scan);
+    block_scan_multi<U, MODE != kTrusted>(c, excl, tot, s.scan, my_flag, s.red, &tile_flag);
     unsigned int agg = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u)

@@ -149,6 +149,13 @@ __device__ __forceinline__ unsigned int opaque(unsigned int v)
     return v;
 }
 
+// The same for a value common to the wave, held in a scalar register.
+__device__ __forceinline__ unsigned int opaque_uniform(unsigned int v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Both bytes of every 16-bit word swapped (UTF-16 big endian <-> little endian).
 __device__ __forceinline__ unsigned int swap16(unsigned int v)
 {

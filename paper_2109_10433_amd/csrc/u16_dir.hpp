@@ -66,20 +66,29 @@ struct U16Dir {
     {
         // Waves without any word in D800..DFFF have nothing to flag; each
         // word then takes 1 + (w >= 0x80) + (w >= 0x800) UTF-8 bytes. The two
-        // words of a dword are tested together as 16-bit halves.
-        u16x2 extra = {0, 0}, plain = {1, 1};
+        // words of a dword are tested together as 16-bit halves: the top bit
+        // of a half of ((x & m) + m) | x, with m = 0x7F80 (0x7800), is set
+        // exactly when its word is >= 0x80 (0x800), and no sum carries into
+        // the next half.
         const u16x2 one = {1, 1}, sur = {0x1B, 0x1B};   // w >> 11 of D800..DFFF
+        u16x2 plain = {1, 1};
 #pragma unroll
         for (int k = 1; k <= 4; ++k) {
             const u16x2 w = __builtin_bit_cast(u16x2, x[k]);
-            const u16x2 t11 = w >> 11;
-            if (COUNT)
-                extra += __builtin_elementwise_min(w >> 7, one) + __builtin_elementwise_min(t11, one);
-            plain = __builtin_elementwise_min(plain, __builtin_elementwise_min(t11 ^ sur, one));
+            plain = __builtin_elementwise_min(plain, __builtin_elementwise_min((w >> 11) ^ sur, one));
         }
         if (!__any(__builtin_bit_cast(unsigned int, plain) != 0x00010001u)) {
             *flag = kNoFlag;
-            return COUNT ? 8u + extra.x + extra.y : 0u;
+            unsigned int count = 8;
+            if (COUNT) {
+#pragma unroll
+                for (int k = 1; k <= 4; ++k) {
+                    const unsigned int g80 = ((x[k] & 0x7F807F80u) + 0x7F807F80u) | x[k];
+                    const unsigned int g800 = ((x[k] & 0x78007800u) + 0x78007800u) | x[k];
+                    count += __popc(g80 & 0x80008000u) + __popc(g800 & 0x80008000u);
+                }
+            }
+            return COUNT ? count : 0u;
         }
         unsigned int count = 0;
         int f = kNoFlag;

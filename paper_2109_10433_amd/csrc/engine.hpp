@@ -240,12 +240,15 @@ __device__ __forceinline__ void end_check(const Doc &d, unsigned long long tile,
 }
 
 // Validation and counting of a staged tile. Returns the per-chunk counts in
-// c[] and lowers flag_min to the first flagged input byte position.
+// c[] and lowers flag_min to the first flagged input byte position; cls gets
+// each sub-tile's wave class for emit (two bits per sub-tile, in a scalar
+// register).
 template <class Dir, int U, bool COUNT>
 __device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsigned char *table, const Doc &d,
                                                unsigned long long tile, unsigned int c[U],
-                                               unsigned long long &flag_min)
+                                               unsigned long long &flag_min, unsigned int &cls)
 {
+    cls = 0;
     // first flag as a 32-bit position inside the tile (no 64-bit chunk
     // positions kept live across the sub-tiles)
     unsigned int rel_min = ~0u;
@@ -254,7 +257,9 @@ __device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsig
         unsigned int x[6];
         t.chunk(u, x);
         int f;
-        c[u] = Dir::template analyze<COUNT>(x, table, &f);
+        unsigned int k;
+        c[u] = Dir::template analyze<COUNT>(x, table, &f, &k);
+        cls |= __builtin_amdgcn_readfirstlane(k) << (2 * u);
         if (f != kNoFlag) {
             const unsigned int rel = (unsigned int)(u * kSub) + threadIdx.x * kChunk + (unsigned int)f * Dir::kInUnit;
             rel_min = rel < rel_min ? rel : rel_min;
@@ -271,9 +276,10 @@ __device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsig
 
 template <class Dir, int U, bool COUNT>
 __device__ __forceinline__ void analyze_tile(const TileRegs<U> &t, const unsigned char *table, const Doc &d,
-                                             unsigned long long tile, unsigned int c[U], unsigned long long &flag_min)
+                                             unsigned long long tile, unsigned int c[U], unsigned long long &flag_min,
+                                             unsigned int &cls)
 {
-    analyze_chunks<Dir, U, COUNT>(t, table, d, tile, c, flag_min);
+    analyze_chunks<Dir, U, COUNT>(t, table, d, tile, c, flag_min, cls);
     if (!tile_is_interior<U>(d, tile)) {
         // Tiles at the input's edges hold zeros outside the input: each zero
         // counts as one unit (an ASCII byte or word), and the only flags they
@@ -345,7 +351,8 @@ __device__ __forceinline__ void scan_tile(const unsigned int *in, const unsigned
         read_chunk(in, u, x);
         const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
         int f;
-        unsigned int c = Dir::template analyze<COUNT>(x, table, &f);
+        unsigned int cls;
+        unsigned int c = Dir::template analyze<COUNT>(x, table, &f, &cls);
         if (f != kNoFlag) {
             const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
             flag_min = pos < flag_min ? pos : flag_min;
@@ -517,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
 template <class Dir, int U, bool SWAP = false>
 __device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Out *stage, const Doc &d,
                                           unsigned long long tile, const unsigned int excl[U], const unsigned int tot[U],
-                                          unsigned long long pos, typename Dir::Out *dst)
+                                          unsigned long long pos, typename Dir::Out *dst, unsigned int cls)
 {
     using Out = typename Dir::Out;
     // output units between dst and the 16-byte aligned address below it
@@ -529,7 +536,7 @@ __device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Ou
         const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
         unsigned int x[6];
         t.template chunk<true>(u, x);
-        Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u));
+        Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u), (cls >> (2 * u)) & 3u);
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
         copy_out<Dir, SWAP>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
@@ -570,10 +577,11 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 
     unsigned long long my_flag = ~0ull;
     unsigned int c[U];
+    unsigned int cls = ~0u;   // wave class per sub-tile; all 3 (unknown) without analysis
     if (MODE == kTrusted)
         count_tile<Dir, U>(t, d, tile, c);
     else
-        analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag);
+        analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag, cls);
     unsigned long long tile_flag = ~0ull;
     unsigned int excl[U], tot[U];
     block_scan_multi<U, MODE != kTrusted>(c, excl, tot, s.scan, my_flag, s.red, &tile_flag);
@@ -616,7 +624,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     }
     if (decode) {
         Out *dst = reinterpret_cast<Out *>(d.dst);
-        emit_tile<Dir, U, SWAP_OUT>(t, s.out + kStageFront, d, tile, excl, tot, pos, dst);
+        emit_tile<Dir, U, SWAP_OUT>(t, s.out + kStageFront, d, tile, excl, tot, pos, dst, cls);
     }
 }
 

@@ -62,8 +62,9 @@ struct U16Dir {
     // start. Called by whole waves (the surrogate test below is a wave vote).
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char * /*table*/,
-                                                           int *flag)
+                                                           int *flag, unsigned int *cls)
     {
+        *cls = 3;   // emit finds its own path
         // Waves without any word in D800..DFFF have nothing to flag; each
         // word then takes 1 + (w >= 0x80) + (w >= 0x800) UTF-8 bytes. The two
         // words of a dword are tested together as 16-bit halves: the top bit
@@ -115,7 +116,7 @@ struct U16Dir {
 
     // Only called for tiles without any flagged word: the output of a sub-tile
     // then fits the staging buffer. Called by whole waves.
-    __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o)
+    __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o, unsigned int /*cls*/)
     {
         // words of three UTF-8 bytes or surrogates anywhere in the wave?
         const unsigned int all = x[1] | x[2] | x[3] | x[4];

@@ -158,10 +158,12 @@ struct U8Dir {
     // of UTF-16 words of the characters that start in the chunk (if COUNT) and
     // sets *flag to the first flagged position relative to the chunk start
     // (kNoFlag if none). Truncation at the input's end is end_truncation's.
-    // Called by whole waves (the narrow test below is a wave vote).
+    // *cls receives the wave's class for emit: 0 no byte >= E0 in x[0..4], 1
+    // no byte >= F0, 2 otherwise. Called by whole waves (the tests below are
+    // wave votes).
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char *table,
-                                                           int *flag)
+                                                           int *flag, unsigned int *cls)
     {
         // Waves with no byte >= E0 hold one- and two-byte characters only
         // (or errors). There the rules of section 3 reduce to: a byte is a
@@ -197,6 +199,7 @@ struct U8Dir {
             }
             if (!__any(bad)) {
                 *flag = kNoFlag;
+                *cls = 0;
                 return count;
             }
         }
@@ -205,6 +208,7 @@ struct U8Dir {
 #pragma unroll
         for (int k = 0; k < 5; ++k)
             F[k] = G[k] & (x[k] << 3);
+        *cls = __any(F[0] | F[1] | F[2] | F[3] | F[4]) ? 2u : 1u;
         unsigned int count = 0;
         if (COUNT) {
 #pragma unroll
@@ -262,23 +266,29 @@ struct U8Dir {
     // Writes the words of the characters that start in the chunk to out[o..].
     // Only called for tiles without any flagged byte, so the chunk is valid
     // UTF-8 (its last character may end in the next chunk) and the output of a
-    // sub-tile fits the staging buffer. Called by whole waves.
-    __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o)
+    // sub-tile fits the staging buffer. cls: the wave's class from analyze, or
+    // 3 if unknown (then found here). Called by whole waves.
+    __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o, unsigned int cls)
     {
         unsigned int lead[4];
-        bool wide = false, pairs = false;   // bytes >= E0, bytes >= F0
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 4; ++k)
             lead[k] = not_cont(x[k + 1]);
-            const unsigned int g = ge_e0(x[k + 1]);
-            wide |= g != 0;
-            pairs |= (g & (x[k + 1] << 3)) != 0;
+        if (cls == 3) {
+            bool wide = false, pairs = false;   // bytes >= E0, bytes >= F0
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const unsigned int g = ge_e0(x[k + 1]);
+                wide |= g != 0;
+                pairs |= (g & (x[k + 1] << 3)) != 0;
+            }
+            cls = !__any(wide) ? 0u : !__any(pairs) ? 1u : 2u;
         }
-        if (!__any(wide)) {
+        if (cls == 0) {
             emit_direct<2>(x, lead, out, o);
             return;
         }
-        if (!__any(pairs)) {
+        if (cls == 1) {
             emit_direct<3>(x, lead, out, o);
             return;
         }

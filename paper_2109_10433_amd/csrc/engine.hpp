@@ -448,6 +448,27 @@ __device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned 
     if (span > Dir::kStageUnits)
         span = Dir::kStageUnits;   // only on invalid input
     const unsigned int groups = (span + G - 1) / G;
+    // The usual case: all of [gbase + shift, gbase + span) inside [0, cap).
+    // Whole groups are then copied with no tests, and threads 0..2G-1 store
+    // the units of the partial groups at either end one by one.
+    const bool fits = gbase + (long long)shift >= 0 && (unsigned long long)(gbase + (long long)span) <= cap;
+    if (fits) {
+        const unsigned int gb = (shift + G - 1) / G, ge = span / G;   // whole groups: [gb, ge)
+        for (unsigned int g = gb + threadIdx.x; g < ge; g += kBlock) {
+            const unsigned int i0 = g * G;
+            const uint4 v = *reinterpret_cast<const uint4 *>(out + i0);
+            *reinterpret_cast<uint4 *>(dst + (gbase + (long long)i0)) = SWAP ? swap16(v) : v;
+        }
+        const unsigned int head_end = gb * G < span ? gb * G : span;
+        const unsigned int tail_begin = ge > gb ? ge * G : head_end;
+        const unsigned int t = threadIdx.x;
+        const unsigned int i = t < G ? shift + t : tail_begin + (t - G);
+        if (t < 2 * G && (t < G ? i < head_end : i < span)) {
+            const Out v = out[i];
+            dst[gbase + (long long)i] = SWAP ? (Out)((v >> 8) | (v << 8)) : v;
+        }
+        return;
+    }
     for (unsigned int g = threadIdx.x; g < groups; g += kBlock) {
         const unsigned int i0 = g * G;
         const long long j0 = gbase + (long long)i0;

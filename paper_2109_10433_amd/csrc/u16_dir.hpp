@@ -47,14 +47,14 @@ struct U16Dir {
     }
 
     // UTF-8 bytes of the chunk's words, without any validation (a high
-    // surrogate four, a low one none).
+    // surrogate four, a low one none): analyze's count, whose flag is not
+    // looked at (its surrogate-free waves take the cheap path; the others
+    // count word by word as below).
     __device__ __forceinline__ static unsigned int count_only(const unsigned int x[6])
     {
-        unsigned int n = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            n += utf8_bytes_of(word(x, j));
-        return n;
+        int f;
+        unsigned int cls;
+        return analyze<true>(x, nullptr, &f, &cls);
     }
 
     // x[0..5] as for UTF-8 input (8 words per chunk, words outside the input

@@ -75,9 +75,9 @@ enum {
 
 /* ------------------------------------------------------------------------
  * Synchronous calls. Each enqueues its kernels on `stream`, waits for that
- * stream, and returns the result. Scratch memory (128 bytes per tile of 20
- * KiB of UTF-8 or 24 KiB of UTF-16 input, hu_workspace_bytes gives the exact
- * figure) comes from a per-device, per-stream cache owned by the library
+ * stream, and returns the result. Scratch memory (128 bytes per tile; tiles
+ * of 20 to 64 KiB of input depending on the operation, hu_workspace_bytes
+ * gives the exact figure) comes from a per-device, per-stream cache owned by the library
  * (freed by hu_shutdown). n = 0 returns {HU_OK, 0}; pointers may then be NULL.
  * A NULL src (or dst with a non-zero capacity) with n > 0 is
  * HU_ERR_INVALID_ARGUMENT. On success exactly `count` units are written to

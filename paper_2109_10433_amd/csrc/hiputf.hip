@@ -67,11 +67,11 @@ KernelChoice choose_kernel(int op)
         return kc;
     }
     switch (op) {
-    case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
-    case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
+    case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUValidate8>), (unsigned long long)kUValidate8 * kSub, false};
+    case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kULength8>), (unsigned long long)kULength8 * kSub, false};
     case HU_OP_CONVERT_UTF8_TO_UTF16LE: return {HU_K(k_convert_u8<kUConvert8, kConvert>), (unsigned long long)kUConvert8 * kSub, true};
-    case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kUScan>), (unsigned long long)kUScan * kSub, false};
-    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kUScan>), (unsigned long long)kUScan * kSub, false};
+    case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kUValidate16>), (unsigned long long)kUValidate16 * kSub, false};
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kULength16>), (unsigned long long)kULength16 * kSub, false};
     default: return {HU_K(k_convert_u16<kUConvert16, kConvert>), (unsigned long long)kUConvert16 * kSub, true};
     }
 #undef HU_K

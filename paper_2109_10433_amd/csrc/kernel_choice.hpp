@@ -11,10 +11,15 @@ namespace hu {
 // Sub-tiles of 4 KiB per tile. Convert tiles: the largest that still fit 64
 // registers (eight waves per SIMD); bigger tiles mean fewer look-backs per
 // byte. UTF-8 input at 6 would spill; UTF-16 input fits 6 when held to eight
-// waves. Validate / length tiles are staged in LDS, 8 sub-tiles each.
+// waves. Validate / length tiles are staged in LDS; their sizes were measured
+// per kernel (4 to 16 sub-tiles; larger tiles keep more bytes in flight per
+// workgroup but fewer workgroups fit a CU).
 constexpr int kUConvert8 = 5;
 constexpr int kUConvert16 = 6;
-constexpr int kUScan = 8;
+constexpr int kUValidate8 = 12;
+constexpr int kULength8 = 8;
+constexpr int kUValidate16 = 16;
+constexpr int kULength16 = 10;
 
 // Internal op flags on top of HU_OP_*: convert without validating (input
 // known to be valid); the UTF-16 side is big endian.

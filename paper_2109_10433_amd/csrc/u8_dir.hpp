@@ -109,26 +109,6 @@ __device__ __forceinline__ unsigned int not_cont(unsigned int x)
     return (y | (y << 1)) & 0x80808080u;
 }
 
-// Decode the character whose lead byte is the low byte of w (little-endian
-// window of the next four bytes) into one UTF-16 word or a surrogate pair.
-// Bit layouts: section 3 (7/11/16/21 payload bits, most significant first;
-// values above U+FFFF become D800 | high ten bits, DC00 | low ten bits of
-// value - 0x10000). Returns the word count; garbage in -> garbage out.
-__device__ __forceinline__ int decode_utf8_char(unsigned int w, unsigned int *u0, unsigned int *u1)
-{
-    unsigned int b0 = w & 0xFFu;
-    unsigned int b1 = (w >> 8) & 0x3Fu, b2 = (w >> 16) & 0x3Fu, b3 = (w >> 24) & 0x3Fu;
-    unsigned int cp2 = ((b0 & 0x1Fu) << 6) | b1;
-    unsigned int cp3 = ((b0 & 0x0Fu) << 12) | (b1 << 6) | b2;
-    unsigned int cp4 = ((b0 & 0x07u) << 18) | (b1 << 12) | (b2 << 6) | b3;
-    unsigned int cp = b0 < 0x80u ? b0 : (b0 < 0xE0u ? cp2 : cp3);
-    unsigned int v = cp4 - 0x10000u;
-    bool pair = b0 >= 0xF0u;
-    *u0 = pair ? (0xD800u | ((v >> 10) & 0x3FFu)) : cp;
-    *u1 = 0xDC00u | (v & 0x3FFu);
-    return pair ? 2 : 1;
-}
-
 struct U8Dir {
     using Out = unsigned short;                       // output code unit
     static constexpr int kInUnit = 1;                 // bytes per input unit
@@ -292,24 +272,7 @@ struct U8Dir {
             emit_direct<3>(x, lead, out, o);
             return;
         }
-        // Surrogate pairs in the wave: one character at a time. (Text dense in
-        // four-byte characters has few leads per chunk; this loop runs once
-        // per lead, where a branch-free form would store at every byte.)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            unsigned int l = lead[k];
-            while (l) {
-                unsigned int m = __builtin_ctz(l) >> 3;
-                l &= l - 1;
-                unsigned int w = __builtin_amdgcn_alignbyte(x[k + 2], x[k + 1], m);
-                unsigned int u0, u1;
-                int nw = decode_utf8_char(w, &u0, &u1);
-                out[o] = (Out)u0;
-                if (nw == 2)
-                    out[o + 1] = (Out)u1;
-                o += nw;
-            }
-        }
+        emit_direct4(x, lead, out, o);
     }
 
     // Decoding without a branch per character, for waves whose characters
@@ -393,6 +356,83 @@ struct U8Dir {
                 const bool guard = k == 0 && b < 3;
                 if (!guard || ib != 0)
                     *p = v;
+            }
+        }
+    }
+
+    // Decoding without a branch per character where the wave holds
+    // four-byte characters (which the paper's vectorised path leaves to its
+    // third case or to scalar code). Leads of one to three bytes give one
+    // word as in emit_direct. A four-byte lead b n1 n2 n3, of value
+    // c = ((b & 7) << 18) | ((n1 & 0x3F) << 12) | ((n2 & 0x3F) << 6) |
+    // (n3 & 0x3F), gives the surrogate pair 0xD800 + ((c - 0x10000) >> 10),
+    // 0xDC00 + (c & 0x3FF) (section 3); for valid bytes these equal, modulo
+    // 2^16, (b << 8) + (n1 << 2) + (n2 >> 4) + 0xE5B8 and ((n2 << 6) & 0x3C0)
+    // + n3 + 0xDB80. Slots count two words per four-byte lead: every position
+    // stores its (last) word at the slot of the last word of the character
+    // at or before it, in descending order as in emit_direct, and a
+    // four-byte lead also stores its first word in the slot before (a second
+    // store, masked to those positions).
+    __device__ __forceinline__ static void emit_direct4(const unsigned int x[6], const unsigned int lead[4], Out *out,
+                                                        unsigned int o)
+    {
+        unsigned int f0[4];   // bytes >= F0
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            f0[k] = ge_e0(x[k + 1]) & (x[k + 1] << 3);
+        unsigned int first[4];
+        first[0] = o;
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            first[k] = first[k - 1] + __popc(lead[k - 1]) + __popc(f0[k - 1]);
+        char *base = reinterpret_cast<char *>(out);
+        const u16x2 k64 = __builtin_bit_cast(u16x2, opaque(0x00400040u));
+#pragma unroll
+        for (int k = 3; k >= 0; --k) {
+            const unsigned int lo = x[k + 1], hi = x[k + 2];
+            // bytes (p, p + 1), (p + 1, p + 2), ... of hi:lo into the halves
+            const unsigned int a2[2] = {__builtin_amdgcn_perm(hi, lo, 0x0C010C00u),
+                                        __builtin_amdgcn_perm(hi, lo, 0x0C030C02u)};
+            const unsigned int b2[2] = {__builtin_amdgcn_perm(hi, lo, 0x0C020C01u),
+                                        __builtin_amdgcn_perm(hi, lo, 0x0C040C03u)};
+            const unsigned int c2[2] = {a2[1], __builtin_amdgcn_perm(hi, lo, 0x0C050C04u)};
+            const unsigned int d2[2] = {b2[1], __builtin_amdgcn_perm(hi, lo, 0x0C060C05u)};
+            const unsigned int lo8 = lo << 8;
+            const unsigned int m[2] = {__builtin_amdgcn_perm(lo, lo8, 0x0A0A0808u),
+                                       __builtin_amdgcn_perm(lo, lo8, 0x0B0B0909u)};
+            unsigned int W[2], H[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const u16x2 av = __builtin_bit_cast(u16x2, a2[h]);
+                const unsigned int two = __builtin_amdgcn_bitop3_b32(a2[h] << 6, b2[h], 0x30803080u, 0x96);
+                unsigned int w = __builtin_amdgcn_bitop3_b32(two, a2[h], m[h], 0xE4);
+                u16x2 t = av * k64 + __builtin_bit_cast(u16x2, b2[h]);
+                t = t * k64 + __builtin_bit_cast(u16x2, c2[h]);
+                t -= (u16x2)(0x2080);
+                const unsigned int below_e0 =
+                    __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
+                w = __builtin_amdgcn_bitop3_b32(w, __builtin_bit_cast(unsigned int, t), below_e0, 0xE4);
+                const u16x2 hs = __builtin_bit_cast(u16x2, a2[h] << 8) + __builtin_bit_cast(u16x2, b2[h] << 2) +
+                                 (__builtin_bit_cast(u16x2, c2[h]) >> 4) + (u16x2)(0xE5B8);
+                const unsigned int ls = ((c2[h] << 6) & 0x03C003C0u) + d2[h] + 0xDB80DB80u;
+                const unsigned int below_f0 =
+                    __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xF0)) >> 15);
+                W[h] = __builtin_amdgcn_bitop3_b32(w, ls, below_f0, 0xE4);
+                H[h] = __builtin_bit_cast(unsigned int, hs);
+            }
+            // byte b of incl2: twice the words of the characters starting at bytes 0..b
+            const unsigned int incl2 = byte_prefix_sum((lead[k] >> 6) + (f0[k] >> 6));
+            const unsigned int a0 = 2u * first[k] - 2u;   // address of slot (first - 1)
+#pragma unroll
+            for (int b = 3; b >= 0; --b) {
+                const unsigned int ib = (incl2 >> (8 * b)) & 0xFFu;
+                unsigned short *p = reinterpret_cast<unsigned short *>(base + a0 + ib);
+                const unsigned short v = (unsigned short)((b & 1) ? (W[b >> 1] >> 16) : W[b >> 1]);
+                const bool guard = k == 0 && b < 3;
+                if (!guard || ib != 0)
+                    *p = v;
+                if ((f0[k] >> (8 * b + 7)) & 1u)
+                    p[-1] = (unsigned short)((b & 1) ? (H[b >> 1] >> 16) : H[b >> 1]);
             }
         }
     }

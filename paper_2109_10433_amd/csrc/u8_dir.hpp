@@ -370,9 +370,10 @@ struct U8Dir {
     // 2^16, (b << 8) + (n1 << 2) + (n2 >> 4) + 0xE5B8 and ((n2 << 6) & 0x3C0)
     // + n3 + 0xDB80. Slots count two words per four-byte lead: every position
     // stores its (last) word at the slot of the last word of the character
-    // at or before it, in descending order as in emit_direct, and a
-    // four-byte lead also stores its first word in the slot before (a second
-    // store, masked to those positions).
+    // at or before it, in descending order as in emit_direct. Before that it
+    // stores its first word one slot lower if it is a four-byte lead, else at
+    // that same slot, where its own second store overwrites it: no store
+    // needs a mask but the guard at the chunk start.
     __device__ __forceinline__ static void emit_direct4(const unsigned int x[6], const unsigned int lead[4], Out *out,
                                                         unsigned int o)
     {
@@ -420,19 +421,23 @@ struct U8Dir {
                 W[h] = __builtin_amdgcn_bitop3_b32(w, ls, below_f0, 0xE4);
                 H[h] = __builtin_bit_cast(unsigned int, hs);
             }
-            // byte b of incl2: twice the words of the characters starting at bytes 0..b
+            // byte b of incl2: twice the words of the characters starting at
+            // bytes 0..b; of incl2h: the same less 2 at four-byte leads (no
+            // byte borrows: such a byte counts at least 4)
             const unsigned int incl2 = byte_prefix_sum((lead[k] >> 6) + (f0[k] >> 6));
+            const unsigned int incl2h = incl2 - (f0[k] >> 6);
             const unsigned int a0 = 2u * first[k] - 2u;   // address of slot (first - 1)
 #pragma unroll
             for (int b = 3; b >= 0; --b) {
                 const unsigned int ib = (incl2 >> (8 * b)) & 0xFFu;
-                unsigned short *p = reinterpret_cast<unsigned short *>(base + a0 + ib);
+                const unsigned int ibh = (incl2h >> (8 * b)) & 0xFFu;
                 const unsigned short v = (unsigned short)((b & 1) ? (W[b >> 1] >> 16) : W[b >> 1]);
+                const unsigned short vh = (unsigned short)((b & 1) ? (H[b >> 1] >> 16) : H[b >> 1]);
                 const bool guard = k == 0 && b < 3;
-                if (!guard || ib != 0)
-                    *p = v;
-                if ((f0[k] >> (8 * b + 7)) & 1u)
-                    p[-1] = (unsigned short)((b & 1) ? (H[b >> 1] >> 16) : H[b >> 1]);
+                if (!guard || ib != 0) {
+                    *reinterpret_cast<unsigned short *>(base + a0 + ibh) = vh;
+                    *reinterpret_cast<unsigned short *>(base + a0 + ib) = v;
+                }
             }
         }
     }

@@ -281,10 +281,11 @@ struct U8Dir {
     // word at byte position p, as if p held a lead b followed by n1, n2 (bit
     // layouts of section 3): b < 0x80: b;  C0..DF: ((b & 0x1F) << 6) |
     // (n1 & 0x3F);  E0..EF: ((b & 0x0F) << 12) | ((n1 & 0x3F) << 6) |
-    // (n2 & 0x3F). With n1, n2 continuation bytes (10xxxxxx) these equal
-    // (b << 6) ^ n1 ^ 0x3080 and, modulo 2^16, (b << 12) + (n1 << 6) + n2 -
-    // 0x2080, which need no masking: words are formed two positions per
-    // register (16-bit halves, packed 16-bit arithmetic for the second) for
+    // (n2 & 0x3F). With n1, n2 continuation bytes (10xxxxxx) the first is
+    // two = (b << 6) ^ n1 ^ 0x3080, and for E0..EF that is 0x800 | the
+    // payload so far, so the second is (two << 6) ^ n2 ^ 0x80 modulo 2^16;
+    // neither needs masking. Words are formed two positions per
+    // register (16-bit halves, packed 16-bit shifts for the second) for
     // all 16 positions, junk at continuation bytes. Every position then stores
     // its word without a branch, positions in descending order, at the slot of
     // the last lead at or before it: a continuation byte's junk lands in the
@@ -304,11 +305,6 @@ struct U8Dir {
         for (int k = 1; k < 4; ++k)
             first[k] = first[k - 1] + __popc(lead[k - 1]);
         char *base = reinterpret_cast<char *>(out);
-        // 64 in both halves, kept in a register so that the products below
-        // stay multiply-adds instead of becoming shifts and adds
-        u16x2 k64 = {64, 64};
-        if constexpr (MAXB >= 3)
-            k64 = __builtin_bit_cast(u16x2, opaque(0x00400040u));
 #pragma unroll
         for (int k = 3; k >= 0; --k) {
             const unsigned int lo = x[k + 1], hi = x[k + 2];   // this dword and the next
@@ -331,14 +327,15 @@ struct U8Dir {
                 if (MAXB >= 3) {
                     const unsigned int c2 = h == 0 ? a2[1] : __builtin_amdgcn_perm(hi, lo, 0x0C050C04u);
                     const u16x2 av = __builtin_bit_cast(u16x2, a2[h]);
-                    // (b * 64 + n1) * 64 + n2 - 0x2080 in each half (multiply-adds)
-                    u16x2 t = av * k64 + __builtin_bit_cast(u16x2, b2[h]);
-                    t = t * k64 + __builtin_bit_cast(u16x2, c2);
-                    t -= (u16x2)(0x2080);
+                    // for a three-byte lead, two = 0x800 | (b & 0x0F) << 6 | (n1 & 0x3F),
+                    // so (two << 6) ^ n2 ^ 0x80 is its word modulo 2^16
+                    const u16x2 t6 = __builtin_bit_cast(u16x2, two) << 6;
+                    const unsigned int three = __builtin_amdgcn_bitop3_b32(__builtin_bit_cast(unsigned int, t6), c2,
+                                                                           0x00800080u, 0x96);
                     // 0xFFFF in the halves whose byte is below 0xE0
                     const unsigned int below =
                         __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
-                    w = __builtin_amdgcn_bitop3_b32(w, __builtin_bit_cast(unsigned int, t), below, 0xE4);
+                    w = __builtin_amdgcn_bitop3_b32(w, three, below, 0xE4);
                 }
                 W[h] = w;
             }
@@ -387,7 +384,6 @@ struct U8Dir {
         for (int k = 1; k < 4; ++k)
             first[k] = first[k - 1] + __popc(lead[k - 1]) + __popc(f0[k - 1]);
         char *base = reinterpret_cast<char *>(out);
-        const u16x2 k64 = __builtin_bit_cast(u16x2, opaque(0x00400040u));
 #pragma unroll
         for (int k = 3; k >= 0; --k) {
             const unsigned int lo = x[k + 1], hi = x[k + 2];
@@ -407,12 +403,12 @@ struct U8Dir {
                 const u16x2 av = __builtin_bit_cast(u16x2, a2[h]);
                 const unsigned int two = __builtin_amdgcn_bitop3_b32(a2[h] << 6, b2[h], 0x30803080u, 0x96);
                 unsigned int w = __builtin_amdgcn_bitop3_b32(two, a2[h], m[h], 0xE4);
-                u16x2 t = av * k64 + __builtin_bit_cast(u16x2, b2[h]);
-                t = t * k64 + __builtin_bit_cast(u16x2, c2[h]);
-                t -= (u16x2)(0x2080);
+                const u16x2 t6 = __builtin_bit_cast(u16x2, two) << 6;
+                const unsigned int three =
+                    __builtin_amdgcn_bitop3_b32(__builtin_bit_cast(unsigned int, t6), c2[h], 0x00800080u, 0x96);
                 const unsigned int below_e0 =
                     __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
-                w = __builtin_amdgcn_bitop3_b32(w, __builtin_bit_cast(unsigned int, t), below_e0, 0xE4);
+                w = __builtin_amdgcn_bitop3_b32(w, three, below_e0, 0xE4);
                 const u16x2 hs = __builtin_bit_cast(u16x2, a2[h] << 8) + __builtin_bit_cast(u16x2, b2[h] << 2) +
                                  (__builtin_bit_cast(u16x2, c2[h]) >> 4) + (u16x2)(0xE5B8);
                 const unsigned int ls = ((c2[h] << 6) & 0x03C003C0u) + d2[h] + 0xDB80DB80u;

@@ -363,11 +363,12 @@ struct U8Dir {
     // word as in emit_direct. A four-byte lead b n1 n2 n3, of value
     // c = ((b & 7) << 18) | ((n1 & 0x3F) << 12) | ((n2 & 0x3F) << 6) |
     // (n3 & 0x3F), gives the surrogate pair 0xD800 + ((c - 0x10000) >> 10),
-    // 0xDC00 + (c & 0x3FF) (section 3); for valid bytes these equal, modulo
-    // 2^16, (b << 8) + (n1 << 2) + (n2 >> 4) + 0xE5B8 and ((n2 << 6) & 0x3C0)
-    // + n3 + 0xDB80. Slots count two words per four-byte lead: every position
-    // stores its (last) word at the slot of the last word of the character
-    // at or before it, in descending order as in emit_direct. Before that it
+    // 0xDC00 + (c & 0x3FF) (section 3). For valid bytes the three-byte
+    // formula of emit_direct gives c >> 6 here, so these are (three >> 4) +
+    // 0xD7C0 and ((n2 << 6) & 0x3C0) + n3 + 0xDB80, modulo 2^16. Slots count
+    // two words per four-byte lead: every position stores its (last) word at
+    // the slot of the last word of the character at or before it, in
+    // descending order as in emit_direct. Before that it
     // stores its first word one slot lower if it is a four-byte lead, else at
     // that same slot, where its own second store overwrites it: no store
     // needs a mask but the guard at the chunk start.
@@ -409,8 +410,9 @@ struct U8Dir {
                 const unsigned int below_e0 =
                     __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
                 w = __builtin_amdgcn_bitop3_b32(w, three, below_e0, 0xE4);
-                const u16x2 hs = __builtin_bit_cast(u16x2, a2[h] << 8) + __builtin_bit_cast(u16x2, b2[h] << 2) +
-                                 (__builtin_bit_cast(u16x2, c2[h]) >> 4) + (u16x2)(0xE5B8);
+                // for a four-byte lead, three is c >> 6 (15 bits), so the first
+                // word is 0xD800 + (c >> 10) - 0x40 = (three >> 4) + 0xD7C0
+                const u16x2 hs = (__builtin_bit_cast(u16x2, three) >> 4) + (u16x2)(0xD7C0);
                 const unsigned int ls = ((c2[h] << 6) & 0x03C003C0u) + d2[h] + 0xDB80DB80u;
                 const unsigned int below_f0 =
                     __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xF0)) >> 15);

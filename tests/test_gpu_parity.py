@@ -123,11 +123,12 @@ def test_small_sizes_and_offsets():
             check_u16_all(text.u16[:n], offset, out_offset=offset % 5)
 
 
-@pytest.mark.parametrize("profile", ["latin", "cyrillic", "cjk", "emoji"])
+@pytest.mark.parametrize("profile", ["latin", "cyrillic", "cjk", "emoji", "mix"])
 def test_decode_paths_at_edges(profile):
     """Each decode path (waves of one/two-byte characters, of up to three
-    bytes, the general one) at the input's edges: sizes around chunk, wave,
-    sub-tile and tile boundaries, cut at character starts, unaligned starts."""
+    bytes, with four-byte characters) at the input's edges: sizes around
+    chunk, wave, sub-tile and tile boundaries, cut at character starts,
+    unaligned starts."""
     text = wl.make_text(profile, 70_000, wl.rng_for("paths", profile))
     sizes = (0, 1, 2, 3, 15, 16, 17, 255, 1023, 1024, 1025, 4095, 4096, 4097,
              16383, 16384, 16385, 24577, 65533, 65541)

@@ -17,7 +17,7 @@ namespace hu {
 constexpr int kUConvert8 = 5;
 constexpr int kUConvert16 = 6;
 constexpr int kUValidate8 = 12;
-constexpr int kULength8 = 8;
+constexpr int kULength8 = 10;
 constexpr int kUValidate16 = 16;
 constexpr int kULength16 = 10;
 

@@ -2,7 +2,7 @@
  * oracle.c - scalar CPU reference for validating UTF-8 <-> UTF-16LE transcoding.
  *
  * TEST INFRASTRUCTURE: see oracle.h. Plain branching code, one character at a
- * time, the "brute-force branching approach" that opens section 4 of the paper:
+ * time, the scalar branching approach that section 4 of the paper opens with:
  * look at the lead byte, branch on the number of continuation bytes.
  * No tables, no intrinsics, no blocking.
  *

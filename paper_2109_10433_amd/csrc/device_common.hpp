@@ -3,9 +3,9 @@
 // Tiling: an input is cut into fixed-size tiles that are processed
 // independently; each tile counts the output code units it will produce and
 // learns where its output starts through a single-pass decoupled look-back over
-// the preceding tiles' published counts. This realises the "interleaved
-// decoding ... by pre-computing the character offsets" that section 7 of
-// Lemire & Mula leaves as future work, with every tile as one piece.
+// the preceding tiles' published counts. This is the interleaved decoding
+// from precomputed character offsets that section 7 of Lemire & Mula leaves
+// as future work, with every tile as one piece.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -30,7 +30,8 @@ struct BatchDoc {                     // mirrors hu_doc
 static_assert(sizeof(BatchDoc) == sizeof(hu_doc), "hu_doc layout");
 
 // Workspace of a batch call:
-//   [BatchHeader (256 B) | status, item_cap words | first_item | err | item_map]
+//   [BatchHeader (256 B) | status, item_cap words | first_item | err | item_map
+//    | two words per block of documents (planning)]
 // The status array starts at a fixed offset; everything after it moves with
 // the call's shape (document count, item capacity). Status words must never
 // hold anything but status words or zeros, so memory that earlier calls used
@@ -43,7 +44,8 @@ struct BatchHeader {
     unsigned long long clear_hi;
     unsigned int epoch;               // tag of this call's status words
     unsigned int hang;                // set if a bounded wait gave up
-    unsigned long long pad[2];
+    unsigned long long overflow;      // 1 if the call's items exceed the item capacity
+    unsigned long long pad;
 };
 static_assert(sizeof(BatchHeader) <= kHeaderBytes, "batch header size");
 
@@ -53,6 +55,7 @@ struct BatchWs {
     unsigned long long *err;          // per document error key
     unsigned long long *item_map;     // per item: document index | tile index << 32
     unsigned long long *status;       // per item look-back status
+    unsigned long long *block;        // per block of documents: UTF-8, UTF-16 items (then their offsets)
     unsigned long long item_cap;
 };
 
@@ -140,56 +143,69 @@ __device__ __forceinline__ void plan_scan2(unsigned long long a, unsigned long l
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kPlanBlock) void k_batch_plan(const BatchDoc *docs, unsigned int n_docs,
-                                                           const uint8_t *src_base, const uint8_t *dst_base,
-                                                           hu_result *results, BatchWs w,
-                                                           unsigned long long tile_bytes)
+// Planning runs in three steps, so that no single workgroup walks all the
+// documents: blocks of kPlanBlock documents (one per thread, coalesced) sum
+// their work items; one workgroup turns the block sums into block offsets
+// and does the call's bookkeeping; the blocks then give every document its
+// first item. Items are numbered UTF-8 documents first, then UTF-16 ones,
+// each in document order.
+
+// Work items of document d (0 if it has none or fails the argument checks,
+// whose result goes to *err).
+__device__ __forceinline__ unsigned long long doc_items(const BatchDoc &b, const uint8_t *src_base,
+                                                        const uint8_t *dst_base, unsigned long long tile_bytes, int *err)
+{
+    *err = doc_check(b, src_base, dst_base);
+    return *err ? 0ull : doc_tiles(b, src_base, tile_bytes);
+}
+
+__global__ __launch_bounds__(kPlanBlock) void k_batch_count(const BatchDoc *docs, unsigned int n_docs,
+                                                            const uint8_t *src_base, const uint8_t *dst_base, BatchWs w,
+                                                            unsigned long long tile_bytes)
 {
     __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
-    __shared__ int s_wrap;
-    const unsigned int per = (n_docs + kPlanBlock - 1) / kPlanBlock;
-    const unsigned int d0 = threadIdx.x * per;
-    const unsigned int d1 = min(d0 + per, n_docs);
+    const unsigned long long d = (unsigned long long)blockIdx.x * kPlanBlock + threadIdx.x;
     unsigned long long c8 = 0, c16 = 0;
-    for (unsigned int d = d0; d < d1; ++d) {
+    if (d < n_docs) {
         const BatchDoc b = docs[d];
-        if (doc_check(b, src_base, dst_base) == 0) {
-            const unsigned long long t = doc_tiles(b, src_base, tile_bytes);
-            if (op_is_u16(b.op))
-                c16 += t;
-            else
-                c8 += t;
-        }
+        int err;
+        const unsigned long long t = doc_items(b, src_base, dst_base, tile_bytes, &err);
+        if (op_is_u16(b.op))
+            c16 = t;
+        else
+            c8 = t;
     }
     unsigned long long e8, e16, t8, t16;
     plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);
-    const bool overflow = t8 + t16 > w.item_cap;
-    for (unsigned int d = d0; d < d1; ++d) {
-        const BatchDoc b = docs[d];
-        int err = doc_check(b, src_base, dst_base);
-        if (err == 0 && overflow)
-            err = HU_ERR_INVALID_ARGUMENT;   // work-item capacity of the workspace exceeded
-        const unsigned long long t = err ? 0 : doc_tiles(b, src_base, tile_bytes);
-        if (t == 0) {
-            hu_result r;
-            r.error = err;
-            r.reserved = 0;
-            r.count = 0;
-            results[d] = r;
-            w.first_item[d] = 0xFFFFFFFFu;
-            continue;
-        }
-        if (op_is_u16(b.op)) {
-            w.first_item[d] = (unsigned int)(t8 + e16);
-            e16 += t;
-        } else {
-            w.first_item[d] = (unsigned int)e8;
-            e8 += t;
-        }
+    if (threadIdx.x == 0) {
+        w.block[2 * blockIdx.x] = t8;
+        w.block[2 * blockIdx.x + 1] = t16;
     }
+}
+
+__global__ __launch_bounds__(kPlanBlock) void k_batch_plan(unsigned int n_blocks, BatchWs w)
+{
+    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ int s_wrap;
+    unsigned long long t8 = 0, t16 = 0;   // items of the blocks so far
+    for (unsigned int g0 = 0; g0 < n_blocks; g0 += kPlanBlock) {
+        const unsigned int g = g0 + threadIdx.x;
+        const unsigned long long a = g < n_blocks ? w.block[2 * g] : 0ull;
+        const unsigned long long b = g < n_blocks ? w.block[2 * g + 1] : 0ull;
+        unsigned long long ea, eb, ta, tb;
+        plan_scan2(a, b, &ea, &eb, &ta, &tb, s_tmp);
+        if (g < n_blocks) {
+            w.block[2 * g] = t8 + ea;          // block offsets, in place of the sums
+            w.block[2 * g + 1] = t16 + eb;
+        }
+        t8 += ta;
+        t16 += tb;
+    }
+    const bool overflow = t8 + t16 > w.item_cap;
     if (threadIdx.x == 0) {
         w.hdr->items8 = overflow ? 0 : t8;
         w.hdr->items16 = overflow ? 0 : t16;
+        w.hdr->overflow = overflow ? 1u : 0u;
         w.hdr->hang = 0;
         // status words of earlier calls' per-document arrays: cleared by fill
         const unsigned long long dirty = w.hdr->dirty_from;
@@ -205,6 +221,44 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_plan(const BatchDoc *docs,
         for (unsigned long long i = threadIdx.x; i < w.item_cap; i += kPlanBlock)
             w.status[i] = 0;
     }
+}
+
+__global__ __launch_bounds__(kPlanBlock) void k_batch_assign(const BatchDoc *docs, unsigned int n_docs,
+                                                             const uint8_t *src_base, const uint8_t *dst_base,
+                                                             hu_result *results, BatchWs w,
+                                                             unsigned long long tile_bytes)
+{
+    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    const unsigned long long d = (unsigned long long)blockIdx.x * kPlanBlock + threadIdx.x;
+    unsigned long long c8 = 0, c16 = 0;
+    int err = 0;
+    bool u16 = false;
+    if (d < n_docs) {
+        const BatchDoc b = docs[d];
+        u16 = op_is_u16(b.op);
+        const unsigned long long t = doc_items(b, src_base, dst_base, tile_bytes, &err);
+        if (u16)
+            c16 = t;
+        else
+            c8 = t;
+    }
+    unsigned long long e8, e16, t8, t16;
+    plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);   // every thread takes part
+    if (d >= n_docs)
+        return;
+    if (err == 0 && w.hdr->overflow != 0)
+        err = HU_ERR_INVALID_ARGUMENT;   // work-item capacity of the workspace exceeded
+    if (err != 0 || c8 + c16 == 0) {
+        hu_result r;
+        r.error = err;
+        r.reserved = 0;
+        r.count = 0;
+        results[d] = r;
+        w.first_item[d] = 0xFFFFFFFFu;
+        return;
+    }
+    w.first_item[d] = u16 ? (unsigned int)(w.hdr->items8 + w.block[2 * blockIdx.x + 1] + e16)
+                          : (unsigned int)(w.block[2 * blockIdx.x] + e8);
 }
 
 // item -> (document, tile) map; every error key back to zero; status words

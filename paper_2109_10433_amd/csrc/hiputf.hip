@@ -142,8 +142,9 @@ constexpr unsigned int kBatchDefaultU = 2;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchLayout {
-    size_t first, err, map, status, total;
+    size_t first, err, map, status, block, total;
     unsigned long long item_cap;
+    unsigned int n_blocks;   // blocks of documents for planning
 };
 
 BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
@@ -156,7 +157,9 @@ BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
     l.first = align256(l.status + 8ull * l.item_cap);
     l.err = align256(l.first + 4ull * n_docs);
     l.map = align256(l.err + 8ull * n_docs);
-    l.total = align256(l.map + 8ull * l.item_cap);
+    l.block = align256(l.map + 8ull * l.item_cap);
+    l.n_blocks = (unsigned int)((n_docs + kPlanBlock - 1ull) / kPlanBlock);
+    l.total = align256(l.block + 16ull * l.n_blocks);
     return l;
 }
 
@@ -206,14 +209,18 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     BatchWs w{reinterpret_cast<BatchHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
               reinterpret_cast<unsigned long long *>(base + l.err),
               reinterpret_cast<unsigned long long *>(base + l.map),
-              reinterpret_cast<unsigned long long *>(base + l.status), l.item_cap};
+              reinterpret_cast<unsigned long long *>(base + l.status),
+              reinterpret_cast<unsigned long long *>(base + l.block), l.item_cap};
     const BatchDoc *bd = reinterpret_cast<const BatchDoc *>(docs);
     const uint8_t *src = reinterpret_cast<const uint8_t *>(src_base);
     uint8_t *dst = reinterpret_cast<uint8_t *>(dst_base);
     const unsigned long long tile_bytes = (unsigned long long)U * kSub;
 
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanBlock), 0, stream, bd, n_docs, src, (const uint8_t *)dst,
-                       results, w, tile_bytes);
+    hipLaunchKernelGGL(k_batch_count, dim3(l.n_blocks), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
+                       (const uint8_t *)dst, w, tile_bytes);
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanBlock), 0, stream, l.n_blocks, w);
+    hipLaunchKernelGGL(k_batch_assign, dim3(l.n_blocks), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
+                       (const uint8_t *)dst, results, w, tile_bytes);
     // enough workgroups for the documents and for clearing the status array
     unsigned long long fill_grid = (n_docs + 255) / 256;
     if (fill_grid < (l.item_cap + 4095) / 4096)

@@ -183,6 +183,33 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_count(const BatchDoc *docs
     }
 }
 
+// The call's totals, the capacity check and the epoch in the header; status
+// words cleared when the epoch wraps. All threads of the workgroup call it.
+__device__ __forceinline__ void plan_bookkeeping(const BatchWs &w, unsigned long long t8, unsigned long long t16,
+                                                 int *s_wrap)
+{
+    const bool overflow = t8 + t16 > w.item_cap;
+    if (threadIdx.x == 0) {
+        w.hdr->items8 = overflow ? 0 : t8;
+        w.hdr->items16 = overflow ? 0 : t16;
+        w.hdr->overflow = overflow ? 1u : 0u;
+        w.hdr->hang = 0;
+        // status words of earlier calls' per-document arrays: cleared by fill
+        const unsigned long long dirty = w.hdr->dirty_from;
+        w.hdr->clear_lo = dirty ? dirty - 1 : w.item_cap;
+        w.hdr->clear_hi = w.item_cap;
+        w.hdr->dirty_from = w.item_cap + 1;
+        const unsigned int e = (w.hdr->epoch + 1u) & kEpochMask;
+        w.hdr->epoch = e;
+        *s_wrap = e == 0;
+    }
+    __syncthreads();
+    if (*s_wrap) {
+        for (unsigned long long i = threadIdx.x; i < w.item_cap; i += kPlanBlock)
+            w.status[i] = 0;
+    }
+}
+
 __global__ __launch_bounds__(kPlanBlock) void k_batch_plan(unsigned int n_blocks, BatchWs w)
 {
     __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
@@ -201,26 +228,26 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_plan(unsigned int n_blocks
         t8 += ta;
         t16 += tb;
     }
-    const bool overflow = t8 + t16 > w.item_cap;
-    if (threadIdx.x == 0) {
-        w.hdr->items8 = overflow ? 0 : t8;
-        w.hdr->items16 = overflow ? 0 : t16;
-        w.hdr->overflow = overflow ? 1u : 0u;
-        w.hdr->hang = 0;
-        // status words of earlier calls' per-document arrays: cleared by fill
-        const unsigned long long dirty = w.hdr->dirty_from;
-        w.hdr->clear_lo = dirty ? dirty - 1 : w.item_cap;
-        w.hdr->clear_hi = w.item_cap;
-        w.hdr->dirty_from = w.item_cap + 1;
-        const unsigned int e = (w.hdr->epoch + 1u) & kEpochMask;
-        w.hdr->epoch = e;
-        s_wrap = e == 0;
+    plan_bookkeeping(w, t8, t16, &s_wrap);
+}
+
+// Document d's first work item, or its result if it has no work (error,
+// empty, or the call's items exceed the workspace's capacity).
+__device__ __forceinline__ void assign_doc(const BatchWs &w, hu_result *results, unsigned long long d, int err,
+                                           unsigned long long items, bool overflow, unsigned long long first)
+{
+    if (err == 0 && overflow)
+        err = HU_ERR_INVALID_ARGUMENT;   // work-item capacity of the workspace exceeded
+    if (err != 0 || items == 0) {
+        hu_result r;
+        r.error = err;
+        r.reserved = 0;
+        r.count = 0;
+        results[d] = r;
+        w.first_item[d] = 0xFFFFFFFFu;
+        return;
     }
-    __syncthreads();
-    if (s_wrap) {
-        for (unsigned long long i = threadIdx.x; i < w.item_cap; i += kPlanBlock)
-            w.status[i] = 0;
-    }
+    w.first_item[d] = (unsigned int)first;
 }
 
 __global__ __launch_bounds__(kPlanBlock) void k_batch_assign(const BatchDoc *docs, unsigned int n_docs,
@@ -244,21 +271,38 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_assign(const BatchDoc *doc
     }
     unsigned long long e8, e16, t8, t16;
     plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);   // every thread takes part
-    if (d >= n_docs)
-        return;
-    if (err == 0 && w.hdr->overflow != 0)
-        err = HU_ERR_INVALID_ARGUMENT;   // work-item capacity of the workspace exceeded
-    if (err != 0 || c8 + c16 == 0) {
-        hu_result r;
-        r.error = err;
-        r.reserved = 0;
-        r.count = 0;
-        results[d] = r;
-        w.first_item[d] = 0xFFFFFFFFu;
-        return;
+    if (d < n_docs)
+        assign_doc(w, results, d, err, c8 + c16, w.hdr->overflow != 0,
+                   u16 ? w.hdr->items8 + w.block[2 * blockIdx.x + 1] + e16 : w.block[2 * blockIdx.x] + e8);
+}
+
+// Planning of a call of at most kPlanBlock documents, all three steps in one
+// workgroup (one launch: small batches, as in serving, wait on it).
+__global__ __launch_bounds__(kPlanBlock) void k_batch_plan1(const BatchDoc *docs, unsigned int n_docs,
+                                                            const uint8_t *src_base, const uint8_t *dst_base,
+                                                            hu_result *results, BatchWs w,
+                                                            unsigned long long tile_bytes)
+{
+    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ int s_wrap;
+    const unsigned int d = threadIdx.x;
+    unsigned long long c8 = 0, c16 = 0;
+    int err = 0;
+    bool u16 = false;
+    if (d < n_docs) {
+        const BatchDoc b = docs[d];
+        u16 = op_is_u16(b.op);
+        const unsigned long long t = doc_items(b, src_base, dst_base, tile_bytes, &err);
+        if (u16)
+            c16 = t;
+        else
+            c8 = t;
     }
-    w.first_item[d] = u16 ? (unsigned int)(w.hdr->items8 + w.block[2 * blockIdx.x + 1] + e16)
-                          : (unsigned int)(w.block[2 * blockIdx.x] + e8);
+    unsigned long long e8, e16, t8, t16;
+    plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);
+    if (d < n_docs)
+        assign_doc(w, results, d, err, c8 + c16, t8 + t16 > w.item_cap, u16 ? t8 + e16 : e8);
+    plan_bookkeeping(w, t8, t16, &s_wrap);
 }
 
 // item -> (document, tile) map; every error key back to zero; status words

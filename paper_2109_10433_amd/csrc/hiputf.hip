@@ -216,11 +216,16 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     uint8_t *dst = reinterpret_cast<uint8_t *>(dst_base);
     const unsigned long long tile_bytes = (unsigned long long)U * kSub;
 
-    hipLaunchKernelGGL(k_batch_count, dim3(l.n_blocks), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
-                       (const uint8_t *)dst, w, tile_bytes);
-    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanBlock), 0, stream, l.n_blocks, w);
-    hipLaunchKernelGGL(k_batch_assign, dim3(l.n_blocks), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
-                       (const uint8_t *)dst, results, w, tile_bytes);
+    if (l.n_blocks == 1) {
+        hipLaunchKernelGGL(k_batch_plan1, dim3(1), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
+                           (const uint8_t *)dst, results, w, tile_bytes);
+    } else {
+        hipLaunchKernelGGL(k_batch_count, dim3(l.n_blocks), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
+                           (const uint8_t *)dst, w, tile_bytes);
+        hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanBlock), 0, stream, l.n_blocks, w);
+        hipLaunchKernelGGL(k_batch_assign, dim3(l.n_blocks), dim3(kPlanBlock), 0, stream, bd, n_docs, src,
+                           (const uint8_t *)dst, results, w, tile_bytes);
+    }
     // enough workgroups for the documents and for clearing the status array
     unsigned long long fill_grid = (n_docs + 255) / 256;
     if (fill_grid < (l.item_cap + 4095) / 4096)

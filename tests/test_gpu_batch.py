@@ -226,6 +226,25 @@ def test_batch_invalid_arguments(texts):
     errs, counts = ok.results_host()
     assert (errs[0], counts[0]) == tuple(oracle.validate_utf8(t8[:60000]))
     assert (errs[1], counts[1]) == tuple(oracle.utf16_length_from_utf8(t8[60000:120000]))
+    # the same check with more documents than one planning block (1024):
+    # 1500 documents of 20000 bytes need 3 items each, the workspace for
+    # total 0 bytes holds 3001
+    many = np.zeros(1500, dtype=hu.DOC_DTYPE)
+    many["src_off"] = (np.arange(1500) % 5) * 20000
+    many["n_units"] = 20000
+    many["op"] = np.arange(1500) % 2
+    say("batch capacity exceeded, 1500 documents")
+    over = hu.Batch(many, big, total_input_bytes=0)
+    assert over.run() == 0
+    errs, _ = over.results_host()
+    assert np.all(errs == hu.INVALID_ARGUMENT)
+    fits = hu.Batch(many, big)
+    assert fits.run() == 0
+    errs, counts = fits.results_host()
+    for i in (0, 1, 1023, 1024, 1499):
+        data = t8[int(many["src_off"][i]):int(many["src_off"][i]) + 20000]
+        want = oracle.validate_utf8(data) if i % 2 == 0 else oracle.utf16_length_from_utf8(data)
+        assert (errs[i], counts[i]) == tuple(want), i
 
 
 def test_batch_graph_replay(texts):
@@ -293,7 +312,7 @@ def test_workspace_reused_across_batch_shapes(texts):
     rng = np.random.default_rng(77)
     t8, t16 = texts
     shapes = [(40, [100, 5000]), (3, [60000]), (300, [10, 200]), (1, [3]), (120, [9000, 30000]),
-              (500, [1, 50]), (20, [100000])]
+              (2500, [1, 400]), (500, [1, 50]), (20, [100000])]
     max_docs = max(n for n, _ in shapes)
     max_total = 4 << 20
     ws = torch.zeros(hu.lib.hu_batch_workspace_bytes(max_docs, max_total) + 256, dtype=torch.uint8, device="cuda")

@@ -19,7 +19,7 @@ constexpr int kBlock = 256;       // threads per workgroup: four wave64
 constexpr int kWaves = kBlock / 64;
 constexpr int kChunk = 16;        // bytes per thread per sub-tile (one dwordx4)
 constexpr int kSub = kBlock * kChunk;    // sub-tile bytes (one coalesced load per thread)
-constexpr int kNoFlag = 0x7FFFFFFF;
+constexpr int kNoFlag = 0x1FFFFFFF;   // no flagged position (all ones >> 3)
 
 // kTrusted: convert input known to be valid (no validation; see the header)
 enum Mode { kValidate = 0, kLength = 1, kConvert = 2, kTrusted = 3 };
@@ -179,6 +179,15 @@ __device__ __forceinline__ unsigned int byte_prefix_sum(unsigned int q)
     unsigned int s, r;
     asm("v_lshl_add_u32 %0, %1, 8, %1" : "=v"(s) : "v"(q));
     asm("v_lshl_add_u32 %0, %1, 16, %1" : "=v"(r) : "v"(s));
+    return r;
+}
+
+// Index of the lowest set bit of v, all ones when v is 0 (the instruction's
+// own result for 0, which the compiler would otherwise test for separately).
+__device__ __forceinline__ unsigned int lowest_bit_or_ones(unsigned int v)
+{
+    unsigned int r;
+    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(v));
     return r;
 }
 

@@ -195,7 +195,8 @@ struct U8Dir {
             for (int k = 0; k < 4; ++k)
                 count += __popc(not_cont(x[k + 1])) + __popc(F[k + 1]);
         }
-        int f = kNoFlag;
+        // 8 * (first flagged position) + 7, or all ones when nothing is flagged
+        unsigned int f8 = ~0u;
         const bool ascii = ((x[1] | x[2] | x[3] | x[4]) & 0x80808080u) == 0;
         if (!ascii || (x[0] & 0x80000000u) != 0) {
             // An all-ASCII chunk can only be flagged if the byte just before
@@ -210,18 +211,22 @@ struct U8Dir {
                 const unsigned int y23 = __builtin_amdgcn_perm(p1, cur, 0x07030602u);   // [c2 p2 c3 p3]
                 const unsigned int i0 = (y01 & 0xFFFFu) >> 4, i1 = y01 >> 20;
                 const unsigned int i2 = (y23 & 0xFFFFu) >> 4, i3 = y23 >> 20;
-                const unsigned int e = (unsigned int)table[i0] | ((unsigned int)table[i1] << 8) |
-                                       ((unsigned int)table[i2] << 16) | ((unsigned int)table[i3] << 24);
+                // entries of bytes 0, 2 and 1, 3 loaded into 16-bit halves
+                const u16x2 e02 = {table[i0], table[i2]}, e13 = {table[i1], table[i3]};
+                const unsigned int e = __builtin_bit_cast(unsigned int, e02) | (__builtin_bit_cast(unsigned int, e13) << 8);
                 // a continuation byte is required exactly where the byte two
                 // back is E0..FF or the byte three back is F0..FF
                 const unsigned int must = __builtin_amdgcn_alignbyte(G[k + 1], G[k], 2) |
                                           __builtin_amdgcn_alignbyte(F[k + 1], F[k], 1);
                 const unsigned int flags = (e | ((e << 1) ^ must)) & 0x80808080u;
-                if (flags && f == kNoFlag)
-                    f = 4 * k + (__builtin_ctz(flags) >> 3);
+                // lowest set bit: 8b + 7 for byte b, all ones if none; OR-ing
+                // 32k keeps all ones and otherwise adds 32k
+                const unsigned int low = lowest_bit_or_ones(flags) | (32u * k);
+                f8 = f8 < low ? f8 : low;
             }
         }
-        *flag = f;
+        static_assert(kNoFlag == (int)(~0u >> 3), "no flag: all ones, shifted");
+        *flag = (int)(f8 >> 3);
         return count;
     }
 

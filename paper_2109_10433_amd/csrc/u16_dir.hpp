@@ -121,7 +121,7 @@ struct U16Dir {
         // words of three UTF-8 bytes or surrogates anywhere in the wave?
         const unsigned int all = x[1] | x[2] | x[3] | x[4];
         if (!__any((all & 0xF800F800u) != 0)) {
-            emit_direct<2>(x, out, o);
+            emit_direct2(x, out, o);
             return;
         }
         bool sur = false;
@@ -166,6 +166,38 @@ struct U16Dir {
                 if (m > 3) out[o + 3] = (Out)b3;
             }
             o += m;
+        }
+    }
+
+    // Encoding of waves whose words are all below U+0800 (one or two bytes,
+    // the first two cases of section 5), two words per register: as 16-bit
+    // halves, the lead byte is w (w < 0x80) or 0xC0 | w >> 6, the second byte
+    // 0x80 | (w & 0x3F). Each word stores both bytes at its output offset,
+    // words in ascending order; the second byte of a one-byte word lands
+    // where the next word starts and is overwritten by it. The last word of
+    // the chunk stores its second byte only if it has one (the next thread's
+    // output starts right after it).
+    __device__ __forceinline__ static void emit_direct2(const unsigned int x[6], Out *out, unsigned int o)
+    {
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const unsigned int v = x[k];
+            const u16x2 w = __builtin_bit_cast(u16x2, v);
+            // 0xFFFF in the halves whose word is below 0x80 (all are below 0x800)
+            const unsigned int small = __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, w - (u16x2)(0x80)) >> 15);
+            const unsigned int lead = __builtin_bit_cast(unsigned int, w >> 6) | 0x00C000C0u;
+            // bitop3 truth tables: 0xE4 (a & c) | (b & ~c), 0xEA (a & b) | c
+            const unsigned int b0 = __builtin_amdgcn_bitop3_b32(v, lead, small, 0xE4);
+            const unsigned int b1 = __builtin_amdgcn_bitop3_b32(v, 0x003F003Fu, 0x00800080u, 0xEA);
+            // bytes per word in each half: 2 - 1 for the small ones
+            const unsigned int n = __builtin_bit_cast(unsigned int, __builtin_bit_cast(u16x2, small) + (u16x2)(2));
+            out[o] = (Out)b0;
+            out[o + 1] = (Out)b1;
+            o += n & 0xFFFFu;
+            out[o] = (Out)(b0 >> 16);
+            if (k < 4 || (n >> 16) == 2u)
+                out[o + 1] = (Out)(b1 >> 16);
+            o += n >> 16;
         }
     }
 

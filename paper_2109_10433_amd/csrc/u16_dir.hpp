@@ -212,6 +212,8 @@ struct U16Dir {
     // chunk's output (the next thread's): the last MAXB - 1 words store a
     // byte only where the chunk's remaining words still reach (words before
     // them are followed by at least MAXB - 1 words of at least one byte).
+    // emit uses MAXB = 3; for waves below U+0800 emit_direct2 is the same
+    // encoding two words at a time.
     template <int MAXB>
     __device__ __forceinline__ static void emit_direct(const unsigned int x[6], Out *out, unsigned int o)
     {

@@ -70,12 +70,43 @@ public:
                 s.staging = nullptr;
                 return HU_ERR_DEVICE;
             }
+            // Write every page once now: the process's first write to a page
+            // of the staging buffer takes a fault, and a batch reaching into
+            // fresh pages would add those faults to its requests' latency.
+            std::memset(s.staging, 0, slot_bytes_);
             if (hipMalloc(&s.ws, ws_bytes) != hipSuccess) {
                 s.ws = nullptr;
                 return HU_ERR_DEVICE;
             }
             s.ws_bytes = ws_bytes;
             if (hu_workspace_init(s.ws, ws_bytes, s.stream) != HU_OK || hipStreamSynchronize(s.stream) != hipSuccess)
+                return HU_ERR_DEVICE;
+        }
+        return warm_up();
+    }
+
+    // Runs two batches of empty documents (one document; more than one
+    // planning block of documents) so that every kernel of the batch path has
+    // been launched once before the first request arrives.
+    int warm_up()
+    {
+        if (plain_)
+            return HU_OK;
+        Slot &s = slots_[0];
+        const uint32_t sizes[2] = {1u, slot_requests_ < 2048u ? slot_requests_ : 2048u};
+        for (uint32_t n : sizes) {
+            const size_t res_off = (n * sizeof(hu_doc) + 255) & ~(size_t)255;
+            if (res_off + n * sizeof(hu_result) > slot_bytes_)
+                continue;
+            std::memset(s.staging, 0, n * sizeof(hu_doc));   // empty documents, op 0 (validate UTF-8)
+            if (hipMemcpyAsync(pool_, s.staging, n * sizeof(hu_doc), hipMemcpyHostToDevice, s.stream) != hipSuccess)
+                return HU_ERR_DEVICE;
+            const int rc = hu_batch_run(reinterpret_cast<const hu_doc *>(pool_), n, 0, pool_, pool_,
+                                        reinterpret_cast<hu_result *>(pool_ + res_off), &tuning_, s.ws, s.ws_bytes,
+                                        s.stream);
+            if (rc != HU_OK)
+                return rc;
+            if (hipStreamSynchronize(s.stream) != hipSuccess)
                 return HU_ERR_DEVICE;
         }
         return HU_OK;
@@ -227,6 +258,12 @@ public:
             pool_ = nullptr;
             return HU_ERR_DEVICE;
         }
+        // Touch the whole pool once before any request is timed (first use of
+        // fresh device memory is slower); the slots' non-blocking streams do
+        // not wait for the null stream, hence the synchronisation.
+        if (hipMemsetAsync(pool_, 0, cfg.pool_bytes, nullptr) != hipSuccess ||
+            hipStreamSynchronize(nullptr) != hipSuccess)
+            return HU_ERR_DEVICE;
         exec_ = new (std::nothrow) HipExecutor(pool_, n_slots, batch_bytes, cfg.max_batch_requests, c.plain != 0,
                                                c.tuning);
         if (exec_ == nullptr)

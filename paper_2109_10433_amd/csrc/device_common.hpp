@@ -20,6 +20,7 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kChunk = 16;        // bytes per thread per sub-tile (one dwordx4)
 constexpr int kSub = kBlock * kChunk;    // sub-tile bytes (one coalesced load per thread)
 constexpr int kNoFlag = 0x1FFFFFFF;   // no flagged position (all ones >> 3)
+constexpr unsigned int kClassUnknown = 7;   // wave class not known: emit finds its own path
 
 // kTrusted: convert input known to be valid (no validation; see the header)
 enum Mode { kValidate = 0, kLength = 1, kConvert = 2, kTrusted = 3 };

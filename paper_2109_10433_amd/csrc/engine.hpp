@@ -241,13 +241,14 @@ __device__ __forceinline__ void end_check(const Doc &d, unsigned long long tile,
 
 // Validation and counting of a staged tile. Returns the per-chunk counts in
 // c[] and lowers flag_min to the first flagged input byte position; cls gets
-// each sub-tile's wave class for emit (two bits per sub-tile, in a scalar
+// each sub-tile's wave class for emit (three bits per sub-tile, in a scalar
 // register).
 template <class Dir, int U, bool COUNT>
 __device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsigned char *table, const Doc &d,
                                                unsigned long long tile, unsigned int c[U],
                                                unsigned long long &flag_min, unsigned int &cls)
 {
+    static_assert(3 * U <= 32, "three class bits per sub-tile");
     cls = 0;
     // first flag as a 32-bit position inside the tile (no 64-bit chunk
     // positions kept live across the sub-tiles)
@@ -259,7 +260,7 @@ __device__ __forceinline__ void analyze_chunks(const TileRegs<U> &t, const unsig
         int f;
         unsigned int k;
         c[u] = Dir::template analyze<COUNT>(x, table, &f, &k);
-        cls |= __builtin_amdgcn_readfirstlane(k) << (2 * u);
+        cls |= __builtin_amdgcn_readfirstlane(k) << (3 * u);
         if (f != kNoFlag) {
             const unsigned int rel = (unsigned int)(u * kSub) + threadIdx.x * kChunk + (unsigned int)f * Dir::kInUnit;
             rel_min = rel < rel_min ? rel : rel_min;
@@ -557,7 +558,7 @@ __device__ __forceinline__ void emit_tile(const TileRegs<U> &t, typename Dir::Ou
         const unsigned int shift = (unsigned int)((dst_mis + pos) % G);
         unsigned int x[6];
         t.template chunk<true>(u, x);
-        Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u), (cls >> (2 * u)) & 3u);
+        Dir::emit(x, stage, shift + excl[u] - (u == 0 ? skip : 0u), (cls >> (3 * u)) & 7u);
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
         copy_out<Dir, SWAP>(stage, shift, tot[u], dst, (long long)pos - (long long)shift, d.cap);
@@ -598,7 +599,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 
     unsigned long long my_flag = ~0ull;
     unsigned int c[U];
-    unsigned int cls = ~0u;   // wave class per sub-tile; all 3 (unknown) without analysis
+    unsigned int cls = ~0u;   // wave class per sub-tile; all 7 (unknown) without analysis
     if (MODE == kTrusted)
         count_tile<Dir, U>(t, d, tile, c);
     else

@@ -64,7 +64,7 @@ struct U16Dir {
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char * /*table*/,
                                                            int *flag, unsigned int *cls)
     {
-        *cls = 3;   // emit finds its own path
+        *cls = kClassUnknown;   // emit finds its own path
         // Waves without any word in D800..DFFF have nothing to flag; each
         // word then takes 1 + (w >= 0x80) + (w >= 0x800) UTF-8 bytes. The two
         // words of a dword are tested together as 16-bit halves: the top bit

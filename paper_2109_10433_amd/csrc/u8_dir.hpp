@@ -139,8 +139,9 @@ struct U8Dir {
     // sets *flag to the first flagged position relative to the chunk start
     // (kNoFlag if none). Truncation at the input's end is end_truncation's.
     // *cls receives the wave's class for emit: 0 no byte >= E0 in x[0..4], 1
-    // no byte >= F0, 2 otherwise. Called by whole waves (the tests below are
-    // wave votes).
+    // no byte >= F0, 4 bytes >= F0 but no lead of two or three bytes (C0..EF)
+    // in x[1..4], 2 otherwise. Called by whole waves (the tests below are wave
+    // votes).
     template <bool COUNT>
     __device__ __forceinline__ static unsigned int analyze(const unsigned int x[6], const unsigned char *table,
                                                            int *flag, unsigned int *cls)
@@ -188,7 +189,16 @@ struct U8Dir {
 #pragma unroll
         for (int k = 0; k < 5; ++k)
             F[k] = G[k] & (x[k] << 3);
-        *cls = __any(F[0] | F[1] | F[2] | F[3] | F[4]) ? 2u : 1u;
+        unsigned int k_cls = 1;
+        if (__any(F[0] | F[1] | F[2] | F[3] | F[4])) {
+            // leads C0..EF in the chunk? (bit 7 of x & x << 1: byte >= C0)
+            unsigned int mid = 0;
+#pragma unroll
+            for (int k = 1; k <= 4; ++k)
+                mid |= x[k] & (x[k] << 1) & ~F[k];
+            k_cls = __any((mid & 0x80808080u) != 0) ? 2u : 4u;
+        }
+        *cls = k_cls;
         unsigned int count = 0;
         if (COUNT) {
 #pragma unroll
@@ -252,14 +262,14 @@ struct U8Dir {
     // Only called for tiles without any flagged byte, so the chunk is valid
     // UTF-8 (its last character may end in the next chunk) and the output of a
     // sub-tile fits the staging buffer. cls: the wave's class from analyze, or
-    // 3 if unknown (then found here). Called by whole waves.
+    // kClassUnknown (then found here, without class 4). Called by whole waves.
     __device__ __forceinline__ static void emit(const unsigned int x[6], Out *out, unsigned int o, unsigned int cls)
     {
         unsigned int lead[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             lead[k] = not_cont(x[k + 1]);
-        if (cls == 3) {
+        if (cls == kClassUnknown) {
             bool wide = false, pairs = false;   // bytes >= E0, bytes >= F0
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
@@ -277,7 +287,11 @@ struct U8Dir {
             emit_direct<3>(x, lead, out, o);
             return;
         }
-        emit_direct4(x, lead, out, o);
+        if (cls == 4) {
+            emit_direct4<false>(x, lead, out, o);
+            return;
+        }
+        emit_direct4<true>(x, lead, out, o);
     }
 
     // Decoding without a branch per character, for waves whose characters
@@ -376,7 +390,10 @@ struct U8Dir {
     // descending order as in emit_direct. Before that it
     // stores its first word one slot lower if it is a four-byte lead, else at
     // that same slot, where its own second store overwrites it: no store
-    // needs a mask but the guard at the chunk start.
+    // needs a mask but the guard at the chunk start. SHORT = false: the wave
+    // has no leads of two or three bytes, so a position's word is its byte
+    // itself unless it is a four-byte lead.
+    template <bool SHORT>
     __device__ __forceinline__ static void emit_direct4(const unsigned int x[6], const unsigned int lead[4], Out *out,
                                                         unsigned int o)
     {
@@ -400,21 +417,24 @@ struct U8Dir {
                                         __builtin_amdgcn_perm(hi, lo, 0x0C040C03u)};
             const unsigned int c2[2] = {a2[1], __builtin_amdgcn_perm(hi, lo, 0x0C050C04u)};
             const unsigned int d2[2] = {b2[1], __builtin_amdgcn_perm(hi, lo, 0x0C060C05u)};
-            const unsigned int lo8 = lo << 8;
-            const unsigned int m[2] = {__builtin_amdgcn_perm(lo, lo8, 0x0A0A0808u),
-                                       __builtin_amdgcn_perm(lo, lo8, 0x0B0B0909u)};
             unsigned int W[2], H[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const u16x2 av = __builtin_bit_cast(u16x2, a2[h]);
                 const unsigned int two = __builtin_amdgcn_bitop3_b32(a2[h] << 6, b2[h], 0x30803080u, 0x96);
-                unsigned int w = __builtin_amdgcn_bitop3_b32(two, a2[h], m[h], 0xE4);
                 const u16x2 t6 = __builtin_bit_cast(u16x2, two) << 6;
                 const unsigned int three =
                     __builtin_amdgcn_bitop3_b32(__builtin_bit_cast(unsigned int, t6), c2[h], 0x00800080u, 0x96);
-                const unsigned int below_e0 =
-                    __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
-                w = __builtin_amdgcn_bitop3_b32(w, three, below_e0, 0xE4);
+                unsigned int w = a2[h];
+                if constexpr (SHORT) {
+                    const unsigned int lo8 = lo << 8;
+                    const unsigned int m = h == 0 ? __builtin_amdgcn_perm(lo, lo8, 0x0A0A0808u)
+                                                  : __builtin_amdgcn_perm(lo, lo8, 0x0B0B0909u);
+                    w = __builtin_amdgcn_bitop3_b32(two, a2[h], m, 0xE4);
+                    const unsigned int below_e0 =
+                        __builtin_bit_cast(unsigned int, __builtin_bit_cast(i16x2, av - (u16x2)(0xE0)) >> 15);
+                    w = __builtin_amdgcn_bitop3_b32(w, three, below_e0, 0xE4);
+                }
                 // for a four-byte lead, three is c >> 6 (15 bits), so the first
                 // word is 0xD800 + (c >> 10) - 0x40 = (three >> 4) + 0xD7C0
                 const u16x2 hs = (__builtin_bit_cast(u16x2, three) >> 4) + (u16x2)(0xD7C0);

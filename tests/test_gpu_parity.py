@@ -166,6 +166,23 @@ def test_characters_split_across_wave_boundaries():
                     check_u16_all(u16)
 
 
+def test_four_byte_waves_with_one_short_lead():
+    """Text of ASCII and four-byte characters only (a wave class whose decode
+    leaves out the two- and three-byte forms) with one two- or three-byte
+    character inserted at chunk positions of the first wave and around the
+    first wave boundary: that wave must take the general four-byte decode and
+    its neighbours the reduced one, with the same words either way."""
+    base = "a\U0001F600b\U0001F30D" * 700
+    for ch in ("\u00e9", "\u4e2d"):
+        for k in list(range(0, 40, 3)) + list(range(400, 420, 2)):
+            text = base[:k] + ch + base[k:]
+            u8 = np.frombuffer(text.encode("utf-8"), np.uint8)
+            u16 = np.frombuffer(text.encode("utf-16-le"), np.uint16)
+            say("four-byte waves with", repr(ch), "at character", k)
+            check_u8_all(u8)
+            check_u16_all(u16)
+
+
 @pytest.mark.parametrize("profile", ["latin", "cyrillic", "cjk"])
 def test_errors_in_short_character_waves(profile):
     """Errors inside text of one/two-byte (Latin, Cyrillic) or up to

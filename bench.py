@@ -685,7 +685,7 @@ def main() -> int:
                    "profiles": profiles, "ops_per_step": ops, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "kernel": "hu::k_convert_u8<5, 2, false>", "traffic_note": traffic_note},
+                     "kernel": "hu::k_convert_u8<6, 2, false>", "traffic_note": traffic_note},
         "cpu_baseline": cpu,
         "copy_ceiling_GBps": round(copy_gbs, 1),
         "batched": batched,

@@ -58,7 +58,9 @@ int max_resident_blocks(const void *kernel)
 
 constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 bits
 
-KernelChoice choose_kernel(int op)
+// n_bytes: the input's size, which picks the UTF-8 -> UTF-16LE tile size (0:
+// the smallest tile any input of the operation may take).
+KernelChoice choose_kernel(int op, unsigned long long n_bytes)
 {
 #define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
     if ((op & kOpFlags) != 0) {   // no kernel for the combination: fn stays null
@@ -69,7 +71,10 @@ KernelChoice choose_kernel(int op)
     switch (op) {
     case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUValidate8>), (unsigned long long)kUValidate8 * kSub, false};
     case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kULength8>), (unsigned long long)kULength8 * kSub, false};
-    case HU_OP_CONVERT_UTF8_TO_UTF16LE: return {HU_K(k_convert_u8<kUConvert8, kConvert>), (unsigned long long)kUConvert8 * kSub, true};
+    case HU_OP_CONVERT_UTF8_TO_UTF16LE:
+        if (n_bytes < kSmallConvert8Bytes)
+            return {HU_K(k_convert_u8<kUConvert8Small, kConvert>), (unsigned long long)kUConvert8Small * kSub, true};
+        return {HU_K(k_convert_u8<kUConvert8, kConvert>), (unsigned long long)kUConvert8 * kSub, true};
     case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kUValidate16>), (unsigned long long)kUValidate16 * kSub, false};
     case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kULength16>), (unsigned long long)kULength16 * kSub, false};
     default: return {HU_K(k_convert_u16<kUConvert16, kConvert>), (unsigned long long)kUConvert16 * kSub, true};
@@ -82,7 +87,7 @@ unsigned long long tiles_for(int op, const void *src, unsigned long long n_units
     const bool u16 = (op & ~kOpFlags) >= HU_OP_VALIDATE_UTF16LE;
     const unsigned long long bytes = u16 ? 2 * n_units : n_units;
     const unsigned long long off = (unsigned long long)((uintptr_t)src & 15u);
-    const unsigned long long tb = choose_kernel(op).tile_bytes;
+    const unsigned long long tb = choose_kernel(op, bytes).tile_bytes;
     return (off + bytes + tb - 1) / tb;
 }
 
@@ -103,7 +108,8 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
         return HU_ERR_INVALID_ARGUMENT;
     if (base_op == HU_OP_CONVERT_UTF8_TO_UTF16LE && ((uintptr_t)dst & 1u))
         return HU_ERR_INVALID_ARGUMENT;
-    if (choose_kernel(op).fn == nullptr)
+    const unsigned long long n_bytes = u16 ? 2 * n : n;
+    if (choose_kernel(op, n_bytes).fn == nullptr)
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned long long n_tiles = n ? tiles_for(op, src, n) : 0;
     if (ws_bytes < kHeaderBytes + 8ull * kStatusStride * n_tiles)
@@ -113,7 +119,7 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     unsigned long long *status = reinterpret_cast<unsigned long long *>((char *)ws + kHeaderBytes);
     unsigned long long status_cap = (ws_bytes - kHeaderBytes) / 8;
 
-    const KernelChoice kc = choose_kernel(op);
+    const KernelChoice kc = choose_kernel(op, n_bytes);
     unsigned long long grid_ll = 1;   // at least one workgroup: with no tiles it only writes the result
     if (kc.one_group_per_tile) {
         if (n_tiles > 0x7FFFFFFFull)
@@ -465,7 +471,8 @@ size_t hu_workspace_bytes(int op, size_t n_units)
         return 0;
     // worst case over source alignments: 15 bytes of offset
     const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
-    const unsigned long long tb = hu::choose_kernel(op).tile_bytes;
+    // the smallest tile the operation may take: enough for any smaller input too
+    const unsigned long long tb = hu::choose_kernel(op, 0).tile_bytes;
     return hu::kHeaderBytes + 8ull * hu::kStatusStride * ((bytes + 15 + tb - 1) / tb);
 }
 

@@ -56,7 +56,7 @@ def test_valid_input_matches_the_oracle(profile):
     say("non-validating, 1 MiB", profile)
     check_valid(text)
     starts8 = text.char_starts_u8
-    for n in (0, 1, 15, 16, 17, 1023, 4097, 20479, 20480, 20481, 24577, 65541, 300_001):
+    for n in (0, 1, 15, 16, 17, 1023, 4097, 20479, 20480, 20481, 24575, 24576, 24577, 65541, 300_001):
         m = int(starts8[np.searchsorted(starts8, n, side="right") - 1])
         for off in (0, 7):
             check_valid(wl.Text(text.cps[:np.searchsorted(starts8, m)], text.utf8_len[:np.searchsorted(starts8, m)],

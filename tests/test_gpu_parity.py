@@ -131,7 +131,7 @@ def test_decode_paths_at_edges(profile):
     unaligned starts."""
     text = wl.make_text(profile, 70_000, wl.rng_for("paths", profile))
     sizes = (0, 1, 2, 3, 15, 16, 17, 255, 1023, 1024, 1025, 4095, 4096, 4097,
-             16383, 16384, 16385, 24577, 65533, 65541)
+             16383, 16384, 16385, 24575, 24576, 24577, 65533, 65541)
     s8, s16 = text.char_starts_u8, text.char_starts_u16
     for offset in (0, 5, 15):
         say(profile, "utf8 edge sizes at offset", offset)
@@ -394,5 +394,6 @@ def test_large_profile_both_directions(profile):
     bad[p] = 0xFF
     say("256 MiB", profile, "bad lead at", p)
     assert hu.validate_utf8(bad) == (hu.BAD_LEAD, p)
+    assert hu.convert_utf8_to_utf16le(bad)[1] == (hu.BAD_LEAD, p)
     del src, words, back, bad
     torch.cuda.empty_cache()

@@ -659,6 +659,16 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
 // last tile writes the call's result once its look-back is complete (every
 // tile publishes its status only after its error report has landed, so by
 // then all reports are in).
+//
+// When the last tile's look-back ends, tiles between its nearest inclusive
+// predecessor and itself may still be in theirs. They hold this call's epoch
+// in a register and read status words tagged with it, so advancing the epoch
+// under them is harmless. Clearing the status words is not: the call that
+// wraps the epoch to 0 (it starts at the largest epoch, which every tile
+// reads before it publishes anything, hence before the last tile can finish)
+// lets each other tile count itself done once its inclusive prefix is out, and
+// the last tile finishes the call and clears the words only when all have.
+// Everything else pays nothing for it.
 template <class Dir, int U, int MODE, bool SWAP_IN, bool SWAP_OUT>
 __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                              unsigned long long *status, unsigned long long status_cap, hu_result *out)
@@ -676,13 +686,41 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
     if (Dir::kNeedsTable)
         build_pair_table(s.table);
     const unsigned int epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool wraps = epoch == kEpochMask;
     const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang, kStatusStride};
     unsigned long long *s_wrap = &s.red[0];
+    unsigned long long wrap_total = 0;   // thread 0 of the last tile, in the wrapping call
     chained_tile<Dir, U, MODE, SWAP_IN, SWAP_OUT>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
-        finish_call(call, hdr, total, status, status_cap, out, s_wrap);
+        if (wraps)
+            wrap_total = total;
+        else
+            finish_call(call, hdr, total, status, status_cap, out, s_wrap);
     });
-    if (tile == n_tiles - 1)
-        wrap_clear(status, status_cap, &s.red[0]);
+    if (!wraps)
+        return;
+    if (tile != n_tiles - 1) {
+        // release: this tile's status words and error report precede the count
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    // every other tile is resident or finished (each published before the
+    // last tile's look-back could end), so this bounded wait only covers the
+    // rest of their look-backs
+    if (threadIdx.x == 0) {
+        unsigned int spins = 0;
+        while (__hip_atomic_load(&hdr->done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+               (unsigned int)(n_tiles - 1)) {
+            if (++spins > kSpinLimit) {
+                // the result reports a device error
+                __hip_atomic_fetch_or(&hdr->hang, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        finish_call(call, hdr, wrap_total, status, status_cap, out, s_wrap);
+    }
+    wrap_clear(status, status_cap, s_wrap);
 }
 
 // MODE: kConvert, or kTrusted for input known to be valid. BE: the UTF-16

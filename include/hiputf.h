@@ -70,7 +70,8 @@ enum {
     HU_ERR_UNPAIRED_SURROGATE = 7, /* UTF-16: high not followed by low, or low not after high */
     HU_ERR_OUTPUT_TOO_SMALL = 16,
     HU_ERR_INVALID_ARGUMENT = 17,
-    HU_ERR_DEVICE = 18
+    HU_ERR_DEVICE = 18,
+    HU_ERR_EXCEEDS_SCRATCH = 19    /* convert_utf8_to_utf16le_noalloc: input above HU_NOALLOC_MAX_BYTES */
 };
 
 /* ------------------------------------------------------------------------
@@ -209,6 +210,28 @@ int convert_valid_utf8_to_utf16le_async(const uint8_t *src, size_t n_bytes, uint
 int convert_valid_utf16le_to_utf8_async(const uint16_t *src, size_t n_words, uint8_t *dst,
                                         size_t dst_cap_bytes, hu_result *d_result,
                                         void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * validating UTF-8 -> UTF-16LE conversion of convert_utf8_to_utf16le_async
+ * with the workspace taken from a static device array of the library
+ * (1.5 MiB per device, held until the process ends) instead of a workspace
+ * argument. It calls no allocating routine. The array's address is looked up
+ * on the first call on each device, and that call also clears it with a
+ * kernel on `stream`; every completed call leaves it ready for the next.
+ * src, dst, dst_cap_words, d_result (a device record) and the result's
+ * meaning are as for convert_utf8_to_utf16le_async; the output is the same.
+ * All calls on one device share the one array: calls that may overlap on a
+ * device (different streams, or graphs replayed concurrently) race and give
+ * wrong results, so they must be ordered on one stream or by events.
+ * Returns HU_OK once enqueued, HU_ERR_EXCEEDS_SCRATCH (nothing enqueued) when
+ * n_bytes > HU_NOALLOC_MAX_BYTES, HU_ERR_INVALID_ARGUMENT as the async call,
+ * or HU_ERR_DEVICE.
+ * ---------------------------------------------------------------------- */
+#define HU_NOALLOC_MAX_BYTES ((size_t)1 << 28)   /* 256 MiB */
+int convert_utf8_to_utf16le_noalloc(const uint8_t *src, size_t n_bytes, uint16_t *dst,
+                                    size_t dst_cap_words, hu_result *d_result, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many documents of any lengths, each with its own operation (any of

@@ -28,6 +28,8 @@ UNPAIRED_SURROGATE = 7
 OUTPUT_TOO_SMALL = 16
 INVALID_ARGUMENT = 17
 DEVICE = 18
+EXCEEDS_SCRATCH = 19
+NOALLOC_MAX_BYTES = 1 << 28
 
 OP_VALIDATE_UTF8 = 0
 OP_UTF16_LENGTH_FROM_UTF8 = 1
@@ -77,6 +79,7 @@ for _name, _args in [
     ("utf8_length_from_utf16be_async", [_p, _sz, _p, _p, _sz, _p]),
     ("convert_utf16be_to_utf8_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
     ("convert_utf8_to_utf16be_async", [_p, _sz, _p, _sz, _p, _p, _sz, _p]),
+    ("convert_utf8_to_utf16le_noalloc", [_p, _sz, _p, _sz, _p, _p]),
 ]:
     getattr(lib, _name).argtypes = _args
     getattr(lib, _name).restype = _i
@@ -140,7 +143,7 @@ EXPORTED = EXPORTED_BATCH + EXPORTED_SERVER + [
     "convert_valid_utf8_to_utf16le_async", "convert_valid_utf16le_to_utf8_async",
     "validate_utf16be", "utf8_length_from_utf16be", "convert_utf16be_to_utf8", "convert_utf8_to_utf16be",
     "validate_utf16be_async", "utf8_length_from_utf16be_async", "convert_utf16be_to_utf8_async",
-    "convert_utf8_to_utf16be_async", "hu_detect_bom",
+    "convert_utf8_to_utf16be_async", "hu_detect_bom", "convert_utf8_to_utf16le_noalloc",
     "hu_workspace_bytes", "hu_workspace_init", "hu_error_name", "hu_shutdown",
 ]
 

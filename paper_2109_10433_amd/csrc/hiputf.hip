@@ -373,6 +373,53 @@ hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, uns
     return *slot->h_result;
 }
 
+// ------------------------------------------------------------ static scratch
+// Workspace of convert_utf8_to_utf16le_noalloc: a file-scope device array
+// (one per device, each at its own address) sized for the largest input it
+// takes. In host code `scratch` names a host-side stand-in, never the device
+// memory: kernels get the address hipGetSymbolAddress returns for the current
+// device, looked up once per device.
+constexpr unsigned long long kNoAllocMaxBytes = HU_NOALLOC_MAX_BYTES;
+constexpr size_t kScratchBytes = 1536u << 10;
+constexpr unsigned long long scratch_need(unsigned long long max_bytes, unsigned long long tile_bytes)
+{
+    // 15 bytes of source alignment offset at most
+    return kHeaderBytes + 8ull * kStatusStride * ((max_bytes + 15 + tile_bytes - 1) / tile_bytes);
+}
+static_assert(kNoAllocMaxBytes >= kSmallConvert8Bytes, "tile choice below");
+static_assert(scratch_need(kNoAllocMaxBytes, (unsigned long long)kUConvert8 * kSub) <= kScratchBytes &&
+                  scratch_need(kSmallConvert8Bytes, (unsigned long long)kUConvert8Small * kSub) <= kScratchBytes,
+              "scratch holds the status words of the largest input");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device (null: not set up)
+
+// The current device's scratch address; on the first call on a device, looks
+// it up and clears the array with a kernel on `stream`. Null on failure.
+void *scratch_for_current_device(hipStream_t stream)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return nullptr;
+        unsigned int *words = reinterpret_cast<unsigned int *>(p);
+        unsigned long long n_words = kScratchBytes / 4;
+        void *args[] = {&words, &n_words};
+        if (hipLaunchKernel(reinterpret_cast<const void *>(&k_fill_zero), dim3(256), dim3(256), args, 0, stream) !=
+            hipSuccess)
+            return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace hu
 
 // ------------------------------------------------------------ C ABI
@@ -569,6 +616,18 @@ int convert_utf8_to_utf16be_async(const uint8_t *src, size_t n_bytes, uint16_t *
                        ws, ws_bytes, (hipStream_t)stream);
 }
 
+int convert_utf8_to_utf16le_noalloc(const uint8_t *src, size_t n_bytes, uint16_t *dst, size_t dst_cap_words,
+                                    hu_result *d_result, void *stream)
+{
+    if (n_bytes > hu::kNoAllocMaxBytes)
+        return HU_ERR_EXCEEDS_SCRATCH;
+    void *ws = hu::scratch_for_current_device((hipStream_t)stream);
+    if (ws == nullptr)
+        return HU_ERR_DEVICE;
+    return hu::enqueue(HU_OP_CONVERT_UTF8_TO_UTF16LE, src, n_bytes, dst, dst_cap_words, d_result, ws,
+                       hu::kScratchBytes, (hipStream_t)stream);
+}
+
 size_t hu_batch_workspace_bytes(uint32_t n_docs, uint64_t total_input_bytes)
 {
     return hu::batch_layout(n_docs, total_input_bytes).total;
@@ -731,6 +790,7 @@ const char *hu_error_name(int error)
     case HU_ERR_OUTPUT_TOO_SMALL: return "OUTPUT_TOO_SMALL";
     case HU_ERR_INVALID_ARGUMENT: return "INVALID_ARGUMENT";
     case HU_ERR_DEVICE: return "DEVICE";
+    case HU_ERR_EXCEEDS_SCRATCH: return "EXCEEDS_SCRATCH";
     default: return "UNKNOWN";
     }
 }

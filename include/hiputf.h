@@ -177,6 +177,13 @@ enum {
 /* Workspace bytes for one call of `op` on n input code units. */
 size_t hu_workspace_bytes(int op, size_t n_units);
 
+/* Input bytes per tile of the kernel that runs `op` (HU_OP_*) on n_units
+ * code units, 0 for an unknown op. A tile is the unit of work that has one
+ * status word in the workspace; tile k covers input bytes [k*T, (k+1)*T)
+ * counted from the 16-byte aligned address at or below src. Host only: no
+ * GPU work, no allocation. */
+size_t hu_tile_bytes(int op, size_t n_units);
+
 /* Zero-fills a workspace with a kernel on `stream` (capturable). */
 int hu_workspace_init(void *ws, size_t ws_bytes, void *stream);
 

@@ -92,6 +92,8 @@ lib.hu_detect_bom.argtypes = [_p, _sz]
 lib.hu_detect_bom.restype = HuBom
 lib.hu_workspace_bytes.argtypes = [_i, _sz]
 lib.hu_workspace_bytes.restype = _sz
+lib.hu_tile_bytes.argtypes = [_i, _sz]
+lib.hu_tile_bytes.restype = _sz
 lib.hu_workspace_init.argtypes = [_p, _sz, _p]
 lib.hu_workspace_init.restype = _i
 lib.hu_batch_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint64]
@@ -144,7 +146,7 @@ EXPORTED = EXPORTED_BATCH + EXPORTED_SERVER + [
     "validate_utf16be", "utf8_length_from_utf16be", "convert_utf16be_to_utf8", "convert_utf8_to_utf16be",
     "validate_utf16be_async", "utf8_length_from_utf16be_async", "convert_utf16be_to_utf8_async",
     "convert_utf8_to_utf16be_async", "hu_detect_bom", "convert_utf8_to_utf16le_noalloc",
-    "hu_workspace_bytes", "hu_workspace_init", "hu_error_name", "hu_shutdown",
+    "hu_workspace_bytes", "hu_tile_bytes", "hu_workspace_init", "hu_error_name", "hu_shutdown",
 ]
 
 

@@ -523,6 +523,14 @@ size_t hu_workspace_bytes(int op, size_t n_units)
     return hu::kHeaderBytes + 8ull * hu::kStatusStride * ((bytes + 15 + tb - 1) / tb);
 }
 
+size_t hu_tile_bytes(int op, size_t n_units)
+{
+    if (op < 0 || op > HU_OP_CONVERT_UTF16LE_TO_UTF8)
+        return 0;
+    const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
+    return hu::choose_kernel(op, bytes).tile_bytes;
+}
+
 int hu_workspace_init(void *ws, size_t ws_bytes, void *stream)
 {
     if (ws == nullptr || ((uintptr_t)ws & 255u) != 0 || ws_bytes < hu::kHeaderBytes)

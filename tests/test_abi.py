@@ -62,3 +62,17 @@ def test_detect_bom_on_the_host():
         assert hu.detect_bom(head) == want, head
     r = hu.lib.hu_detect_bom(None, 3)
     assert (r.encoding, r.length) == (hu.BOM_NONE, 0)
+
+
+def test_tile_bytes_on_the_host():
+    """hu_tile_bytes is host-only: tile sizes per operation (4 KiB sub-tiles;
+    the UTF-8 -> UTF-16LE conversion takes larger tiles from 64 MiB on), 0
+    for an unknown op."""
+    from paper_2109_10433_amd import binding as hu
+    sub = 4096
+    want = {0: 12 * sub, 1: 10 * sub, 2: 5 * sub, 3: 16 * sub, 4: 10 * sub, 5: 6 * sub}
+    for op, tb in want.items():
+        assert hu.lib.hu_tile_bytes(op, 1000) == tb
+    assert hu.lib.hu_tile_bytes(2, (64 << 20) - 1) == 5 * sub
+    assert hu.lib.hu_tile_bytes(2, 64 << 20) == 6 * sub
+    assert hu.lib.hu_tile_bytes(6, 10) == 0 and hu.lib.hu_tile_bytes(-1, 10) == 0

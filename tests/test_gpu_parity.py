@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     from paper_2109_10433_amd import binding as hu
-    TILE = 4096
+
+SUB = 4096       # sub-tile bytes: one 16-byte load per thread of a 256-thread workgroup
 
 
 def _stream():
@@ -220,21 +221,22 @@ def test_power_of_two_sizes():
             check_u16_all(text.u16[:n], offset=2 * (k % 8))
 
 
-# ---------------------------------------------------------------- errors near tile boundaries
+# ---------------------------------------------------------------- errors near sub-tile boundaries
+# (tile boundaries proper: tests/test_gpu_tile_boundaries.py)
 
-def test_errors_around_tile_boundaries():
-    text = wl.make_text("mix", 3 * TILE + 100, wl.rng_for("tiles"))
+def test_errors_around_sub_tile_boundaries():
+    text = wl.make_text("mix", 3 * SUB + 100, wl.rng_for("tiles"))
     rng = np.random.default_rng(3)
     starts = text.char_starts_u8
     for offset in (0, 5):
-        for boundary in (TILE, 2 * TILE):
+        for boundary in (SUB, 2 * SUB):
             b = boundary - offset       # tile boundaries in input coordinates
             for d in range(-6, 7):
                 for kind in wl.UTF8_ERROR_KINDS:
                     i = int(np.searchsorted(starts, b + d))
                     pos = int(starts[min(i, starts.size - 2)])
                     data, p = wl.inject_utf8_error(text.u8, starts, kind, rng, position=pos)
-                    say("tile boundary", boundary, "offset", offset, "delta", d, kind, "at", p)
+                    say("sub-tile boundary", boundary, "offset", offset, "delta", d, kind, "at", p)
                     ov = tuple(oracle.validate_utf8(data))
                     assert gpu_u8("validate", data, offset)[0] == ov
                     if ov[0] != 0:
@@ -249,13 +251,13 @@ def test_errors_around_tile_boundaries():
     # UTF-16: unpaired surrogates around word tile boundaries
     w = text.u16
     for offset in (0, 6):
-        for boundary in (TILE // 2, TILE):
+        for boundary in (SUB // 2, SUB):
             b = boundary - offset // 2
             for d in range(-3, 4):
                 for val in (0xD800, 0xDBFF, 0xDC00, 0xDFFF):
                     data = w.copy()
                     data[b + d] = val
-                    say("utf16 tile boundary", boundary, "delta", d, hex(val))
+                    say("utf16 sub-tile boundary", boundary, "delta", d, hex(val))
                     check_u16_all(data, offset)
 
 
@@ -369,25 +371,20 @@ def test_large_profile_both_directions(profile):
     src = torch.from_numpy(t.u8).cuda()
     say("256 MiB", profile, "utf8 -> utf16")
     words, r = hu.convert_utf8_to_utf16le(src)
-    assert r == (0, t.u16.size)
-    assert np.array_equal(words.cpu().numpy().view(np.uint16), t.u16)     # CPython codec output
-    assert hu.validate_utf8(src) == (0, t.u8.size)
-    assert hu.utf16_length_from_utf8(src) == (0, t.u16.size)
+    ow, orr = oracle.convert_utf8_to_utf16le(t.u8)
+    assert r == tuple(orr) == (0, t.u16.size)
+    assert np.array_equal(words.cpu().numpy().view(np.uint16), ow)        # the oracle's whole output
+    assert hu.validate_utf8(src) == tuple(oracle.validate_utf8(t.u8))
+    assert hu.utf16_length_from_utf8(src) == tuple(oracle.utf16_length_from_utf8(t.u8))
     say("256 MiB", profile, "utf16 -> utf8")
     back, r2 = hu.convert_utf16le_to_utf8(words)
-    assert r2 == (0, t.u8.size)
-    assert np.array_equal(back.cpu().numpy(), t.u8)
-    assert hu.validate_utf16le(words) == (0, t.u16.size)
-    assert hu.utf8_length_from_utf16le(words) == (0, t.u8.size)
-    # the oracle on a sample of windows, each starting at a character boundary
-    rng = np.random.default_rng(5)
+    ob, orr2 = oracle.convert_utf16le_to_utf8(ow)
+    assert r2 == tuple(orr2) == (0, t.u8.size)
+    assert np.array_equal(back.cpu().numpy(), ob)
+    assert hu.validate_utf16le(words) == tuple(oracle.validate_utf16le(ow))
+    assert hu.utf8_length_from_utf16le(words) == tuple(oracle.utf8_length_from_utf16le(ow))
+    del ow, ob
     starts = t.char_starts_u8
-    for _ in range(8):
-        i = int(rng.integers(0, starts.size - 200_000))
-        a, b = int(starts[i]), int(starts[i + 100_000])
-        ow, orr = oracle.convert_utf8_to_utf16le(t.u8[a:b])
-        w0 = int(t.char_starts_u16[i])
-        assert np.array_equal(words[w0:w0 + ow.size].cpu().numpy().view(np.uint16), ow)
     # one error late in the buffer
     bad = src.clone()
     p = int(starts[starts.size - 1000])

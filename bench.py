@@ -4,9 +4,19 @@ one MI355X.
 A step is one pass of the whole single-buffer hot path over the large-buffer
 workload: for each of four 256 MiB UTF-8 profiles (Latin, Cyrillic, CJK,
 Emoji) convert UTF-8 -> UTF-16LE, convert UTF-16LE -> UTF-8, both length
-functions and both validations, each one kernel launch of the library's async
-entry points with caller-owned workspaces (no allocation in the timed region).
-Inputs are resident in HBM before timing starts.
+functions and both validations (and the non-validating and big-endian
+conversions), each one kernel launch of the library's async entry points with
+caller-owned workspaces (no allocation in the timed region). Inputs are
+resident in HBM before timing starts; each profile has two input copies that
+successive steps use in turn, and every operation writes its own output
+buffer. After the timed steps every result and every output is compared with
+the CPU oracle's, whose single-thread timings on the same inputs are the CPU
+baseline legs (both directions, length, validation; GB/s and Gchar/s).
+Per operation and profile: minimum, median and mean over the steps, and
+whether the mean lies within 1 % of the minimum.
+
+The 1 MiB mixed buffer and its six copies with one injected error each are
+timed 2000 times each (per-launch HIP events), results against the oracle.
 
 `value` is the validating UTF-8 -> UTF-16LE throughput in GB/s of algorithmic
 bytes (input bytes read + output bytes written), aggregated over the four
@@ -19,12 +29,17 @@ documents run as one launch per document (the plain path):
     batch call, with sub-tile count and workgroups per CU from the autotuner;
   * 10 000 UTF-16LE documents (uniform 64 B - 4 MiB, mixed profiles, 0.5% with
     an unpaired surrogate) converted to UTF-8 by replaying a captured HIP graph.
-Then open-loop Poisson request traces (10k, 50k and 200k requests/s; sizes
+Every document's result (and the output of every UTF-8 document, of a
+seeded sample of 1000 UTF-16 ones) is compared with the oracle's, run over
+the documents on up to 16 host threads (the CPU figure for the batches).
+Then open-loop Poisson request traces of 10 s (10k, 50k and 200k requests/s; sizes
 log-normal, median 4 KiB, 16 B - 16 MiB; 70% UTF-8 -> UTF-16LE, 30% the
 reverse; 1% invalid) are replayed from host memory through the continuous-
 batching server (8 GiB device pool) and through the plain path (one request at
 a time: copy in, one launch, copy out, wait), with p50/p99 latency from arrival
-to output in host memory.
+to output in host memory; every request's result (error kind and position
+included) is compared with the oracle's, and the oracle's own per-request
+latency is sampled beside it.
 Last, an input-size sweep (1 B - 256 MiB of the mixed profile, both
 directions) times single calls back to back and one synchronous call at a
 time, with the CPU oracle on the same inputs up to 16 MiB.
@@ -75,6 +90,119 @@ def _time_on_stream(fn, stream, reps):
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
+def _per_launch_times(fn, stream, reps):
+    """Seconds of each of reps calls of fn(), from a HIP event pair around
+    each launch on `stream` (numpy array)."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    ev[-1][1].synchronize()
+    return np.array([a.elapsed_time(b) * 1e-3 for a, b in ev])
+
+
+def _timing_stats(ts) -> dict:
+    """Minimum, median and mean of repeated timings (microseconds), and the
+    repeatability check of the paper's protocol: the mean within 1 % of the
+    minimum."""
+    import numpy as np
+    ts = np.asarray(ts, dtype=np.float64)
+    mn, md, mean = float(ts.min()), float(np.median(ts)), float(ts.mean())
+    return {"reps": int(ts.size), "us_min": round(mn * 1e6, 2), "us_median": round(md * 1e6, 2),
+            "us_mean": round(mean * 1e6, 2), "mean_over_min_pct": round(100 * (mean / mn - 1), 2),
+            "mean_within_1pct_of_min": bool(mean <= 1.01 * mn)}
+
+
+def _workers() -> int:
+    """Host threads for the oracle's parallel legs: the cores the process may
+    use, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _pool_map(fn, chunks, workers):
+    """fn over chunks in a thread pool (the oracle's C calls release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, chunks))
+
+
+def _chunks(n, parts):
+    step = max(1, -(-n // parts))
+    return [(a, min(a + step, n)) for a in range(0, n, step)]
+
+
+def _cpu_info() -> dict:
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    from oracle.build import CFLAGS
+    return {"cpu_model": model, "host_cores_visible": os.cpu_count(), "oracle_compiler": "gcc",
+            "oracle_flags": " ".join(CFLAGS)}
+
+
+def bench_single_1mib(args, hu, wl, dev, stream):
+    """One 1 MiB buffer of mixed text (70/10/15/5 % one- to four-byte
+    characters) and six copies with one injected error of each kind:
+    validating UTF-8 -> UTF-16LE, R repetitions each (per-launch HIP events,
+    minimum / median / mean), every result and the clean copy's words checked
+    against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    text = wl.single_buffer(wl.MIB)
+    copies = [("clean", text.u8, None)] + list(wl.single_buffer_with_errors(text))
+    n = text.u8.size
+    ws = hu.workspace(hu.OP_CONVERT_UTF8_TO_UTF16LE, n, dev)
+    wsp, wsb = hu.workspace_ptr(ws)
+    dst = torch.empty(n, dtype=torch.int16, device=dev)
+    rec = torch.zeros(16, dtype=torch.uint8, device=dev)
+    sh = hu.stream_handle(stream)
+    out = {"workload": "1 MiB mixed text (70/10/15/5 % of characters with 1/2/3/4 UTF-8 bytes) and six copies "
+                       "with one injected error each, validating UTF-8 -> UTF-16LE",
+           "bytes": n, "copies": {}}
+    for kind, data, pos in copies:
+        src = torch.from_numpy(data.copy()).to(dev)
+        call = (lambda src=src: hu.lib.convert_utf8_to_utf16le_async(src.data_ptr(), n, dst.data_ptr(), n,
+                                                                      rec.data_ptr(), wsp, wsb, sh))
+        for _ in range(50):
+            if call() != 0:
+                raise RuntimeError("1 MiB buffer: enqueue failed")
+        ts = _per_launch_times(call, stream, args.reps_1mib)
+        t_b2b = _time_on_stream(call, stream, args.reps_1mib)
+        r = hu.result_from_device(rec)
+        ow, orr = oracle.convert_utf8_to_utf16le(data)
+        if tuple(r) != tuple(orr):
+            raise RuntimeError(f"1 MiB buffer {kind}: result {tuple(r)} != oracle {tuple(orr)}")
+        if orr.error == 0 and not np.array_equal(dst[:orr.count].cpu().numpy().view(np.uint16), ow):
+            raise RuntimeError("1 MiB buffer: words differ from the oracle's")
+        e = _timing_stats(ts)
+        e["us_back_to_back_mean"] = round(t_b2b * 1e6, 2)
+        e["result"] = {"error": hu.error_name(r.error), "count": int(r.count)}
+        if kind == "clean":
+            moved = n + 2 * int(r.count)
+            e["GBps_at_min"] = round(moved / (e["us_min"] * 1e-6) / 1e9, 1)
+            e["GBps_at_median"] = round(moved / (e["us_median"] * 1e-6) / 1e9, 1)
+        else:
+            e["injected_at"] = int(pos)
+        out["copies"][kind.lower()] = e
+    out["oracle_agrees"] = True
+    log("1 MiB buffer: " + ", ".join(f"{k} {v['us_median']} us" for k, v in out["copies"].items()))
+    return out
+
+
 def _plain_launches(hu, fns, stream, passes):
     """One library launch per document (fns: one callable each); mean seconds
     per pass over all documents, HIP events on the stream."""
@@ -119,9 +247,8 @@ def bench_utf8_documents(args, hu, wl, dev, stream):
         hu.graph_destroy(g)
     errs, counts = batch.results_host()
     bad = errs != 0
-    if not np.array_equal(bad, b.injected):
-        raise RuntimeError("utf8 documents: documents with errors differ from the injected set")
     out_bytes = int(2 * counts[~bad].sum())
+    oracle_check, cpu_leg = _oracle_utf8_documents(b, lens, errs, counts, dst)
 
     # plain: one async convert launch per document, results to their own records
     recs = torch.zeros((n, 16), dtype=torch.uint8, device=dev)
@@ -163,7 +290,53 @@ def bench_utf8_documents(args, hu, wl, dev, stream):
                                           "docs_per_s": round(n / t_sync, 1)},
         "speedup_batched_vs_plain": round(t_plain / t_batch, 1),
         "speedup_batched_vs_sync_calls": round(t_sync / t_batch, 1),
+        "oracle_agrees": oracle_check,
+        "cpu_oracle": cpu_leg,
     }
+
+
+def _oracle_utf8_documents(b, lens, errs, counts, dst):
+    """Every document of the UTF-8 batch through the oracle (host threads,
+    each a run of documents): (error, count) of each, and the words of every
+    document without an error, compared with the batch's results and output.
+    Returns (check record, CPU timing of the oracle pass)."""
+    import numpy as np
+
+    import oracle
+    n = lens.size
+    offs = b.offsets[:-1].astype(np.uint64)
+    total = int(b.offsets[-1])
+    ref = np.zeros(total + 8, dtype=np.uint16)        # the batch's layout: document d at word offs[d]
+    src_addr = b.data.ctypes.data + offs
+    dst_addr = ref.ctypes.data + 2 * offs
+    workers = _workers()
+    parts = _chunks(n, 8 * workers)
+
+    def run(ab):
+        a, e = ab
+        return oracle.many_convert_at(False, src_addr[a:e], lens[a:e], dst_addr[a:e], lens[a:e])
+    t0 = time.perf_counter()
+    res = _pool_map(run, parts, workers)
+    t_cpu = time.perf_counter() - t0
+    oe = np.concatenate([r[0] for r in res])
+    oc = np.concatenate([r[1] for r in res])
+    if not (np.array_equal(oe, errs) and np.array_equal(oc, counts)):
+        k = int(np.nonzero((oe != errs) | (oc != counts))[0][0])
+        raise RuntimeError(f"utf8 documents: doc {k}: batch {(errs[k], counts[k])} != oracle {(oe[k], oc[k])}")
+    got = dst[:2 * total].cpu().numpy().view(np.uint16).copy()
+    for d in np.nonzero(oe != 0)[0]:              # output of a failed call is unspecified
+        a, e = int(offs[d]), int(offs[d] + lens[d])
+        got[a:e] = 0
+        ref[a:e] = 0
+    if not np.array_equal(got, ref[:total]):
+        k = int(np.nonzero(got != ref[:total])[0][0])
+        raise RuntimeError(f"utf8 documents: output word {k} differs from the oracle's")
+    moved = total + int(2 * oc[oe == 0].sum())
+    check = {"docs_checked": int(n), "results_equal": True, "docs_with_output_compared": int((oe == 0).sum()),
+             "output_words_compared": int(oc[oe == 0].sum())}
+    cpu = {"docs_per_s": round(n / t_cpu, 1), "GBps": round(moved / t_cpu / 1e9, 3), "threads": workers,
+           "seconds": round(t_cpu, 3)}
+    return check, cpu
 
 
 def bench_utf16_documents(args, hu, wl, dev, stream):
@@ -211,12 +384,8 @@ def bench_utf16_documents(args, hu, wl, dev, stream):
         torch.cuda.synchronize()
         hu.graph_destroy(g)
     errs, counts = batch.results_host()
-    want_err = np.where(spec.injected, 7, 0)
-    want_cnt = np.where(spec.injected, 2 * np.maximum(spec.inj_pos, 0), expect).astype(np.uint64)
-    if not (np.array_equal(errs, want_err) and np.array_equal(counts, want_cnt)):
-        k = int(np.nonzero((errs != want_err) | (counts != want_cnt))[0][0])
-        raise RuntimeError(f"utf16 documents: doc {k}: {(errs[k], counts[k])} != {(want_err[k], want_cnt[k])}")
-    out_bytes = int(expect.sum())
+    oracle_check, cpu_leg = _oracle_utf16_documents(args, spec, cap, dst_off, errs, counts, dst)
+    out_bytes = int(counts[errs == 0].sum())
 
     recs = torch.zeros((n, 16), dtype=torch.uint8, device=dev)
     ws = hu.workspace(hu.OP_CONVERT_UTF16LE_TO_UTF8, int(spec.length.max()), dev)
@@ -246,7 +415,75 @@ def bench_utf16_documents(args, hu, wl, dev, stream):
         "plain_per_document_launches": {"ms": round(t_plain * 1e3, 3), "docs_per_s": round(n / t_plain, 1),
                                         "GBps": round(algo / t_plain / 1e9, 1)},
         "speedup_batched_vs_plain": round(t_plain / t_graph, 2),
+        "oracle_agrees": oracle_check,
+        "cpu_oracle": cpu_leg,
     }
+
+
+def _oracle_utf16_documents(args, spec, cap, dst_off, errs, counts, dst):
+    """Every document of the UTF-16 batch converted by the oracle with the
+    batch's capacity (host threads, runs of documents, each into its own
+    scratch output): (error, count) of each compared with the batch's; the
+    output bytes of a seeded sample of documents compared with the batch's
+    output. Returns (check record, CPU timing of the oracle pass)."""
+    import numpy as np
+
+    import oracle
+    n = spec.length.size
+    lens = spec.length.astype(np.uint64)
+    injected = np.nonzero(spec.injected)[0]
+    own = {int(d): spec.doc(int(d)) for d in injected}    # documents with an injected error: own copies
+    src_addr = np.zeros(n, dtype=np.uint64)
+    for d in range(n):
+        if d in own:
+            src_addr[d] = own[d].ctypes.data
+        else:
+            src_addr[d] = spec.pools[spec.profiles[d]].u16.ctypes.data + 2 * int(spec.start[d])
+    rng = np.random.default_rng(wl_seed_sample(spec))
+    sample = np.sort(rng.choice(n, size=min(n, args.docs16_sample), replace=False))
+    in_sample = np.zeros(n, dtype=bool)
+    in_sample[sample] = True
+    gpu_out = {int(d): dst[int(dst_off[d]):int(dst_off[d]) + int(counts[d])].cpu().numpy()
+               for d in sample if errs[d] == 0}
+    workers = _workers()
+    parts = _chunks(n, 64 * workers)
+    mismatched = []
+
+    def run(ab):
+        a, e = ab
+        caps = cap[a:e].astype(np.uint64)
+        buf = np.empty(int(caps.sum()) + 1, dtype=np.uint8)
+        offs = np.concatenate([[0], np.cumsum(caps)[:-1]]).astype(np.uint64)
+        r = oracle.many_convert_at(True, src_addr[a:e], lens[a:e], buf.ctypes.data + offs, caps)
+        for k in range(e - a):
+            d = a + k
+            if in_sample[d] and r[0][k] == 0 and d in gpu_out:
+                o = int(offs[k])
+                if not np.array_equal(buf[o:o + int(r[1][k])], gpu_out[d]):
+                    mismatched.append(d)
+        return r
+    t0 = time.perf_counter()
+    res = _pool_map(run, parts, workers)
+    t_cpu = time.perf_counter() - t0
+    oe = np.concatenate([r[0] for r in res])
+    oc = np.concatenate([r[1] for r in res])
+    if not (np.array_equal(oe, errs) and np.array_equal(oc, counts)):
+        k = int(np.nonzero((oe != errs) | (oc != counts))[0][0])
+        raise RuntimeError(f"utf16 documents: doc {k}: batch {(errs[k], counts[k])} != oracle {(oe[k], oc[k])}")
+    if mismatched:
+        raise RuntimeError(f"utf16 documents: output of doc {mismatched[0]} differs from the oracle's")
+    moved = 2 * int(lens.sum()) + int(oc[oe == 0].sum())
+    check = {"docs_checked": int(n), "results_equal": True, "docs_with_errors": int((oe != 0).sum()),
+             "output_sample_docs": int(len(gpu_out)),
+             "output_sample_bytes": int(sum(v.size for v in gpu_out.values()))}
+    cpu = {"docs_per_s": round(n / t_cpu, 1), "GBps": round(moved / t_cpu / 1e9, 3), "threads": workers,
+           "seconds": round(t_cpu, 3)}
+    return check, cpu
+
+
+def wl_seed_sample(spec) -> int:
+    """Seed of the output sample of the UTF-16 batch (fixed per batch size)."""
+    return 210910433 + 4 + int(spec.length.size)
 
 
 def _trace_records(hu, tr, arena):
@@ -269,8 +506,59 @@ def _trace_records(hu, tr, arena):
     return rec
 
 
-def _serve_once(hu, srv, tr, rec, n_use, label):
-    """Replays the first n_use requests of the trace; checks every result."""
+def _oracle_requests(tr, rec):
+    """The oracle's result for every request of a trace: with the capacity of
+    the worst case (one word per UTF-8 byte, three bytes per UTF-16 word) a
+    conversion's result is its length function's (the same first error, the
+    same count), which the oracle computes for each request where it lies in
+    host memory (host threads, runs of requests). Returns (errors, counts,
+    CPU seconds)."""
+    import numpy as np
+
+    import oracle
+    n = rec.size
+    errs = np.zeros(n, dtype=np.int32)
+    counts = np.zeros(n, dtype=np.uint64)
+    workers = _workers()
+    t0 = time.perf_counter()
+    for utf16 in (False, True):
+        idx = np.nonzero((tr.ops == 5) == utf16)[0]
+        addrs, units = rec["src"][idx], rec["n_units"][idx]
+
+        def run(ab, addrs=addrs, units=units, utf16=utf16):
+            a, e = ab
+            return oracle.many_at(1, utf16, addrs[a:e], units[a:e])
+        res = _pool_map(run, _chunks(idx.size, 16 * workers), workers)
+        if res:
+            errs[idx] = np.concatenate([r[0] for r in res])
+            counts[idx] = np.concatenate([r[1] for r in res])
+    return errs, counts, time.perf_counter() - t0
+
+
+def _oracle_request_latency(tr, rec, n_sample):
+    """Host time of single oracle conversions, one request at a time (the
+    first n_sample requests of the trace): the CPU beside the served path."""
+    import numpy as np
+
+    import oracle
+    m = min(n_sample, rec.size)
+    cap = int(max(rec["dst_cap"][:m].max(), 1))
+    scratch = np.empty(2 * cap, dtype=np.uint8)
+    lat = np.zeros(m, dtype=np.int64)
+    for k in range(m):
+        utf16 = bool(tr.ops[k] == 5)
+        t0 = time.perf_counter_ns()
+        oracle.convert_raw(utf16, int(rec["src"][k]), int(rec["n_units"][k]), scratch.ctypes.data,
+                           int(rec["dst_cap"][k]))
+        lat[k] = time.perf_counter_ns() - t0
+    return {"requests": int(m), "threads": 1, "p50_us": round(float(np.percentile(lat, 50)) * 1e-3, 2),
+            "p99_us": round(float(np.percentile(lat, 99)) * 1e-3, 2),
+            "mean_us": round(float(lat.mean()) * 1e-3, 2)}
+
+
+def _serve_once(hu, srv, tr, rec, n_use, label, want_err, want_cnt):
+    """Replays the first n_use requests of the trace; checks every result
+    (kind and position of errors included) against the oracle's."""
     import numpy as np
     srv.reset_stats()
     t0 = time.perf_counter()
@@ -279,13 +567,11 @@ def _serve_once(hu, srv, tr, rec, n_use, label):
     st = srv.stats()
     err = comps["error"]
     cnt = comps["count"]
-    inv = tr.invalid[:n_use]
-    want = tr.expect_count[:n_use]
-    bad = ((err != 0) != inv) | (~inv & (cnt != want))
+    bad = (err != want_err[:n_use]) | (cnt != want_cnt[:n_use])
     if np.any(bad):
         k = int(np.nonzero(bad)[0][0])
-        raise RuntimeError(f"{label}: request {k}: result ({err[k]}, {cnt[k]}) unexpected "
-                           f"(invalid={bool(inv[k])}, expected count {want[k]})")
+        raise RuntimeError(f"{label}: request {k}: result ({err[k]}, {cnt[k]}) != oracle "
+                           f"({want_err[k]}, {want_cnt[k]})")
     lat = comps["latency_ns"].astype(np.float64)
     ends = tr.arrival_ns[:n_use] + comps["latency_ns"]
     makespan = float(ends.max() - tr.arrival_ns[0]) * 1e-9
@@ -302,6 +588,8 @@ def _serve_once(hu, srv, tr, rec, n_use, label):
         "mean_batch": round(st["mean_batch"], 1),
         "device_busy_frac": round(st["device_ns"] * 1e-9 / makespan, 3),
         "replay_wall_s": round(wall, 2),
+        "oracle_agrees": True,
+        "requests_with_errors": int((err != 0).sum()),
     }
 
 
@@ -385,18 +673,23 @@ def bench_serving(args, hu, wl):
             n = rec.size
             log(f"serving {rate:.0f}/s: {n} requests, {sum(x.nbytes for x in tr.inputs) / 1e9:.2f} GB input, "
                 f"generated in {time.time() - t_gen:.1f}s")
-            served = _serve_once(hu, srv, tr, rec, n, f"served {rate:.0f}/s")
+            want_err, want_cnt, t_or = _oracle_requests(tr, rec)
+            log(f"serving {rate:.0f}/s: oracle results of all requests in {t_or:.1f}s")
+            served = _serve_once(hu, srv, tr, rec, n, f"served {rate:.0f}/s", want_err, want_cnt)
             log(f"serving {rate:.0f}/s: served p50 {served['p50_ms']} ms p99 {served['p99_ms']} ms "
                 f"{served['GBps']} GB/s")
             n_plain = min(n, args.serve_plain_max)
-            pl = _serve_once(hu, plain, tr, rec, n_plain, f"plain {rate:.0f}/s")
+            pl = _serve_once(hu, plain, tr, rec, n_plain, f"plain {rate:.0f}/s", want_err, want_cnt)
             log(f"serving {rate:.0f}/s: plain p50 {pl['p50_ms']} ms p99 {pl['p99_ms']} ms {pl['GBps']} GB/s")
             out["rates"][f"{rate:.0f}"] = {
                 "requests": int(n),
                 "offered_input_GBps": round(sum(x.nbytes for x in tr.inputs) / args.serve_seconds / 1e9, 3),
                 "served": served,
                 "plain_per_request": pl,
+                "oracle_requests_checked": int(n),
             }
+            if "oracle_latency" not in out:
+                out["oracle_latency"] = _oracle_request_latency(tr, rec, args.serve_oracle_sample)
     finally:
         srv.close()
         plain.close()
@@ -410,22 +703,31 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size-mib", type=int, default=256, help="UTF-8 bytes per profile (MiB)")
     ap.add_argument("--profiles", default="latin,cyrillic,cjk,emoji")
+    ap.add_argument("--copies", type=int, default=2,
+                    help="input copies per profile, used in turn by successive steps (no repetition re-reads "
+                         "an input the one before it left in the Infinity Cache)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="comma list of ops to run (default all): "
                     "u8u16,u16u8,len8,len16,val8,val16,nv8u16,nv16u8,u8u16be,u16beu8 "
                     "(nv: non-validating conversions; be: UTF-16 big endian)")
+    ap.add_argument("--no-1mib", action="store_true", help="skip the 1 MiB single-buffer workload")
+    ap.add_argument("--reps-1mib", type=int, default=2000, help="repetitions of each 1 MiB call")
     ap.add_argument("--no-batched", action="store_true", help="skip the two batched document workloads")
     ap.add_argument("--docs8", type=int, default=100_000, help="UTF-8 documents in the batched workload")
     ap.add_argument("--docs16", type=int, default=10_000, help="UTF-16LE documents in the batched workload")
+    ap.add_argument("--docs16-sample", type=int, default=1000,
+                    help="UTF-16 documents whose output bytes are compared with the oracle's")
     ap.add_argument("--plain-passes", type=int, default=2, help="timed passes of the per-document launches")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving traces")
     ap.add_argument("--no-sweep", action="store_true", help="skip the input-size sweep")
     ap.add_argument("--sync-docs", type=int, default=10_000,
                     help="documents of the UTF-8 batch also run as synchronous calls (a prefix)")
     ap.add_argument("--serve-rates", default="10000,50000,200000", help="Poisson arrival rates (requests/s)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each arrival trace")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each arrival trace")
     ap.add_argument("--serve-plain-max", type=int, default=100_000,
                     help="requests of each trace replayed through the plain path (a prefix)")
+    ap.add_argument("--serve-oracle-sample", type=int, default=20_000,
+                    help="requests timed one at a time through the oracle (latency context)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build is single-GPU (got --gpus {args.gpus}); "
@@ -446,24 +748,31 @@ def main() -> int:
     n_bytes = args.size_mib * wl.MIB
     ops_all = ["u8u16", "u16u8", "len8", "len16", "val8", "val16", "nv8u16", "nv16u8", "u8u16be", "u16beu8"]
     ops = [o for o in (args.only.split(",") if args.only else ops_all) if o]
+    copies = max(1, args.copies)
+    # ops with an output, and the buffer each writes (never shared: every
+    # output is checked after the timed steps)
+    out16_ops = [o for o in ("u8u16", "nv8u16", "u8u16be") if o in ops]
+    out8_ops = [o for o in ("u16u8", "nv16u8", "u16beu8") if o in ops]
 
     # ---------------------------------------------------------------- inputs
     data = {}
     t_gen = time.time()
     for p in profiles:
         t = wl.large_profile(p, n_bytes)
-        src8 = torch.from_numpy(t.u8.copy()).to(dev)
-        src16 = torch.from_numpy(t.u16.view(np.int16).copy()).to(dev)
         n8, n16 = int(t.u8.size), int(t.u16.size)
-        data[p] = dict(text=t, src8=src8, src16=src16, n8=n8, n16=n16,
-                       dst16=torch.empty(n8, dtype=torch.int16, device=dev),
-                       dst8=torch.empty(n8 + 64, dtype=torch.uint8, device=dev))
+        src8 = [torch.from_numpy(t.u8.copy()).to(dev) for _ in range(copies)]
+        src16 = [torch.from_numpy(t.u16.view(np.int16).copy()).to(dev) for _ in range(copies)]
+        d = dict(text=t, src8=src8, src16=src16, n8=n8, n16=n16, out={})
         if {"u8u16be", "u16beu8"} & set(ops):
             # the same text in UTF-16BE: each word's two bytes swapped
-            data[p]["src16be"] = src16.view(torch.uint8).view(-1, 2).flip(1).contiguous().view(torch.int16).view(-1)
-            data[p]["dst16be"] = torch.empty(n8, dtype=torch.int16, device=dev)
-            data[p]["dst8be"] = torch.empty(n8 + 64, dtype=torch.uint8, device=dev)
-        log(f"{p}: {n8} B UTF-8, {n16} words UTF-16")
+            d["src16be"] = [x.view(torch.uint8).view(-1, 2).flip(1).contiguous().view(torch.int16).view(-1)
+                            for x in src16]
+        for o in out16_ops:
+            d["out"][o] = torch.empty(n8, dtype=torch.int16, device=dev)
+        for o in out8_ops:
+            d["out"][o] = torch.empty(n8 + 64, dtype=torch.uint8, device=dev)
+        data[p] = d
+        log(f"{p}: {n8} B UTF-8, {n16} words UTF-16, {copies} input copies")
     log(f"inputs generated and uploaded in {time.time() - t_gen:.1f}s")
 
     max8 = max(d["n8"] for d in data.values())
@@ -473,91 +782,131 @@ def main() -> int:
     w8p, w8b = hu.workspace_ptr(ws8)
     w16p, w16b = hu.workspace_ptr(ws16)
 
-    calls = []   # (op, profile, fn, algorithmic bytes, expected (error, count))
-    for p in profiles:
+    def profile_calls(p, c):
+        """The launches of profile p on its input copy c: (op, profile, fn(rec), algorithmic bytes)."""
         d = data[p]
         n8, n16 = d["n8"], d["n16"]
+        s8, s16 = d["src8"][c].data_ptr(), d["src16"][c].data_ptr()
+        s16be = d["src16be"][c].data_ptr() if "src16be" in d else 0
+        o = {k: v.data_ptr() for k, v in d["out"].items()}
         spec = {
-            "u8u16": (lambda rec, d=d: hu.lib.convert_utf8_to_utf16le_async(
-                d["src8"].data_ptr(), d["n8"], d["dst16"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
-                n8 + 2 * n16, (0, n16)),
-            "nv8u16": (lambda rec, d=d: hu.lib.convert_valid_utf8_to_utf16le_async(
-                d["src8"].data_ptr(), d["n8"], d["dst16"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
-                n8 + 2 * n16, (0, n16)),
-            "nv16u8": (lambda rec, d=d: hu.lib.convert_valid_utf16le_to_utf8_async(
-                d["src16"].data_ptr(), d["n16"], d["dst8"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
-                2 * n16 + n8, (0, n8)),
-            "u16u8": (lambda rec, d=d: hu.lib.convert_utf16le_to_utf8_async(
-                d["src16"].data_ptr(), d["n16"], d["dst8"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
-                2 * n16 + n8, (0, n8)),
-            "u8u16be": (lambda rec, d=d: hu.lib.convert_utf8_to_utf16be_async(
-                d["src8"].data_ptr(), d["n8"], d["dst16be"].data_ptr(), d["n8"], rec, w8p, w8b, sh),
-                n8 + 2 * n16, (0, n16)),
-            "u16beu8": (lambda rec, d=d: hu.lib.convert_utf16be_to_utf8_async(
-                d["src16be"].data_ptr(), d["n16"], d["dst8be"].data_ptr(), d["n8"] + 64, rec, w16p, w16b, sh),
-                2 * n16 + n8, (0, n8)),
-            "len8": (lambda rec, d=d: hu.lib.utf16_length_from_utf8_async(
-                d["src8"].data_ptr(), d["n8"], rec, w8p, w8b, sh), n8, (0, n16)),
-            "len16": (lambda rec, d=d: hu.lib.utf8_length_from_utf16le_async(
-                d["src16"].data_ptr(), d["n16"], rec, w16p, w16b, sh), 2 * n16, (0, n8)),
-            "val8": (lambda rec, d=d: hu.lib.validate_utf8_async(
-                d["src8"].data_ptr(), d["n8"], rec, w8p, w8b, sh), n8, (0, n8)),
-            "val16": (lambda rec, d=d: hu.lib.validate_utf16le_async(
-                d["src16"].data_ptr(), d["n16"], rec, w16p, w16b, sh), 2 * n16, (0, n16)),
+            "u8u16": (lambda rec: hu.lib.convert_utf8_to_utf16le_async(
+                s8, n8, o["u8u16"], n8, rec, w8p, w8b, sh), n8 + 2 * n16),
+            "nv8u16": (lambda rec: hu.lib.convert_valid_utf8_to_utf16le_async(
+                s8, n8, o["nv8u16"], n8, rec, w8p, w8b, sh), n8 + 2 * n16),
+            "u16u8": (lambda rec: hu.lib.convert_utf16le_to_utf8_async(
+                s16, n16, o["u16u8"], n8 + 64, rec, w16p, w16b, sh), 2 * n16 + n8),
+            "nv16u8": (lambda rec: hu.lib.convert_valid_utf16le_to_utf8_async(
+                s16, n16, o["nv16u8"], n8 + 64, rec, w16p, w16b, sh), 2 * n16 + n8),
+            "u8u16be": (lambda rec: hu.lib.convert_utf8_to_utf16be_async(
+                s8, n8, o["u8u16be"], n8, rec, w8p, w8b, sh), n8 + 2 * n16),
+            "u16beu8": (lambda rec: hu.lib.convert_utf16be_to_utf8_async(
+                s16be, n16, o["u16beu8"], n8 + 64, rec, w16p, w16b, sh), 2 * n16 + n8),
+            "len8": (lambda rec: hu.lib.utf16_length_from_utf8_async(s8, n8, rec, w8p, w8b, sh), n8),
+            "len16": (lambda rec: hu.lib.utf8_length_from_utf16le_async(s16, n16, rec, w16p, w16b, sh), 2 * n16),
+            "val8": (lambda rec: hu.lib.validate_utf8_async(s8, n8, rec, w8p, w8b, sh), n8),
+            "val16": (lambda rec: hu.lib.validate_utf16le_async(s16, n16, rec, w16p, w16b, sh), 2 * n16),
         }
-        for op in ops:
-            fn, nbytes, expect = spec[op]
-            calls.append((op, p, fn, nbytes, expect))
+        return [(op, p) + spec[op] for op in ops]
 
-    recs = torch.zeros((len(calls), 16), dtype=torch.uint8, device=dev)
-    rec_ptrs = [recs[i].data_ptr() for i in range(len(calls))]
+    calls = [[x for p in profiles for x in profile_calls(p, c)] for c in range(copies)]
+    n_calls = len(calls[0])
+    recs = torch.zeros((copies, n_calls, 16), dtype=torch.uint8, device=dev)
+    rec_ptrs = [[recs[c, i].data_ptr() for i in range(n_calls)] for c in range(copies)]
 
-    def run_step(events=None):
-        for i, (op, p, fn, _, _) in enumerate(calls):
+    def run_step(s, events=None):
+        c = s % copies
+        for i, (op, p, fn, _) in enumerate(calls[c]):
             if events is not None:
                 events[i][0].record(stream)
-            rc = fn(rec_ptrs[i])
+            rc = fn(rec_ptrs[c][i])
             if rc != 0:
                 raise RuntimeError(f"{op} {p}: enqueue failed with {hu.error_name(rc)}")
             if events is not None:
                 events[i][1].record(stream)
 
-    for _ in range(args.warmup):
-        run_step()
+    for s in range(args.warmup):
+        run_step(s)
     torch.cuda.synchronize()
 
-    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in calls]
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(n_calls)]
           for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        run_step(ev[s])
+        run_step(s, ev[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    # ---------------------------------------------------------------- check results
-    host = recs.cpu().numpy()
-    for i, (op, p, _, _, expect) in enumerate(calls):
-        r = hu.HuResult.from_buffer_copy(host[i].tobytes())
-        if (r.error, r.count) != expect:
-            raise RuntimeError(f"{op} {p}: result {(r.error, r.count)} != expected {expect}")
-    for p in profiles:
-        d = data[p]
-        if "u8u16" in ops and not torch.equal(d["dst16"][:d["n16"]], d["src16"]):
-            raise RuntimeError(f"{p}: UTF-16 output differs from the reference encoding")
-        if "u16u8" in ops and not torch.equal(d["dst8"][:d["n8"]], d["src8"]):
-            raise RuntimeError(f"{p}: UTF-8 output differs from the reference encoding")
-        if "u8u16be" in ops and not torch.equal(d["dst16be"][:d["n16"]], d["src16be"]):
-            raise RuntimeError(f"{p}: UTF-16BE output differs from the reference encoding")
-        if "u16beu8" in ops and not torch.equal(d["dst8be"][:d["n8"]], d["src8"]):
-            raise RuntimeError(f"{p}: UTF-8 output of the UTF-16BE input differs from the reference encoding")
-
     # ---------------------------------------------------------------- timings
     per = {}
-    for i, (op, p, _, nbytes, _) in enumerate(calls):
-        ts = [ev[s][i][0].elapsed_time(ev[s][i][1]) * 1e-3 for s in range(args.steps)]
-        per[(op, p)] = dict(bytes=nbytes, mean_s=float(np.mean(ts)), min_s=float(np.min(ts)),
-                            median_s=float(np.median(ts)))
+    for i, (op, p, _, nbytes) in enumerate(calls[0]):
+        ts = np.array([ev[s][i][0].elapsed_time(ev[s][i][1]) * 1e-3 for s in range(args.steps)])
+        per[(op, p)] = dict(bytes=nbytes, mean_s=float(ts.mean()), min_s=float(ts.min()),
+                            median_s=float(np.median(ts)), stats=_timing_stats(ts))
+
+    # ---------------------------------------------------------------- oracle: results, outputs, CPU legs
+    # Every result of the timed steps and every output buffer against the
+    # oracle's, which also gives the single-thread CPU figures (each leg timed
+    # on its own: the same inputs, one pass).
+    host = recs.cpu().numpy()
+    cpu_legs = {op: {"bytes": 0, "chars": 0, "s": 0.0, "profiles": {}} for op in
+                ("u8u16", "u16u8", "len8", "len16", "val8", "val16")}
+    oracle_checked = {"results": 0, "outputs": 0, "output_units": 0}
+    import oracle
+
+    def timed(fn, *a):
+        t1 = time.perf_counter()
+        r = fn(*a)
+        return r, time.perf_counter() - t1
+
+    for p in profiles:
+        d = data[p]
+        t = d["text"]
+        n8, n16, chars = d["n8"], d["n16"], int(t.cps.size)
+        (ow, r8), s_u8u16 = timed(oracle.convert_utf8_to_utf16le, t.u8)
+        (ob, r16), s_u16u8 = timed(oracle.convert_utf16le_to_utf8, t.u16)
+        rl8, s_len8 = timed(oracle.utf16_length_from_utf8, t.u8)
+        rl16, s_len16 = timed(oracle.utf8_length_from_utf16le, t.u16)
+        rv8, s_val8 = timed(oracle.validate_utf8, t.u8)
+        rv16, s_val16 = timed(oracle.validate_utf16le, t.u16)
+        for op, sec, nb in (("u8u16", s_u8u16, n8 + 2 * n16), ("u16u8", s_u16u8, 2 * n16 + n8),
+                            ("len8", s_len8, n8), ("len16", s_len16, 2 * n16),
+                            ("val8", s_val8, n8), ("val16", s_val16, 2 * n16)):
+            leg = cpu_legs[op]
+            leg["bytes"] += nb
+            leg["chars"] += chars
+            leg["s"] += sec
+            leg["profiles"][p] = {"GBps": round(nb / sec / 1e9, 3), "Gchar_per_s": round(chars / sec / 1e9, 3)}
+        want = {"u8u16": r8, "nv8u16": r8, "u8u16be": r8, "u16u8": r16, "nv16u8": r16, "u16beu8": r16,
+                "len8": rl8, "len16": rl16, "val8": rv8, "val16": rv16}
+        for c in range(copies):
+            for i, (op, pp, _, _) in enumerate(calls[c]):
+                if pp != p:
+                    continue
+                r = hu.HuResult.from_buffer_copy(host[c, i].tobytes())
+                if (r.error, r.count) != tuple(want[op]):
+                    raise RuntimeError(f"{op} {p}: result {(r.error, r.count)} != oracle {tuple(want[op])}")
+                oracle_checked["results"] += 1
+        if r8.error != 0 or r16.error != 0:
+            raise RuntimeError(f"{p}: the oracle rejects the profile text")
+        ow_t = torch.from_numpy(ow.view(np.int16)).to(dev)
+        for o in out16_ops:
+            ref = ow_t if o != "u8u16be" else ow_t.view(torch.uint8).view(-1, 2).flip(1).contiguous().view(torch.int16).view(-1)
+            if not torch.equal(d["out"][o][:r8.count], ref):
+                raise RuntimeError(f"{o} {p}: output differs from the oracle's")
+            oracle_checked["outputs"] += 1
+            oracle_checked["output_units"] += int(r8.count)
+        del ow_t, ow
+        ob_t = torch.from_numpy(ob).to(dev)
+        for o in out8_ops:
+            if not torch.equal(d["out"][o][:r16.count], ob_t):
+                raise RuntimeError(f"{o} {p}: output differs from the oracle's")
+            oracle_checked["outputs"] += 1
+            oracle_checked["output_units"] += int(r16.count)
+        del ob_t, ob
+    log(f"large buffers: {oracle_checked['results']} results and {oracle_checked['outputs']} outputs "
+        f"equal to the oracle's")
 
     def agg(op):
         keys = [k for k in per if k[0] == op]
@@ -570,8 +919,10 @@ def main() -> int:
         detail.setdefault(op, {})[p] = {
             "GBps": round(v["bytes"] / v["mean_s"] / 1e9, 1),
             "GBps_best": round(v["bytes"] / v["min_s"] / 1e9, 1),
-            "us_mean": round(v["mean_s"] * 1e6, 1),
+            "GBps_median": round(v["bytes"] / v["median_s"] / 1e9, 1),
             "pct_peak": round(100 * v["bytes"] / v["mean_s"] / 1e9 / PEAK_HBM_GBS, 1),
+            **{k: v["stats"][k] for k in ("us_min", "us_median", "us_mean", "mean_over_min_pct",
+                                           "mean_within_1pct_of_min")},
         }
     for op in ops:
         detail[op]["aggregate_GBps"] = round(agg(op), 1)
@@ -596,7 +947,7 @@ def main() -> int:
     avg_dur = sum(per[k]["mean_s"] for k in launches) / len(launches)
     achieved = avg_bytes / avg_dur / 1e9
 
-    # practical ceiling: device-to-device copy of 256 MiB (read + write)
+    # practical ceiling: device-to-device copy of the profile size (read + write)
     cbuf_a = torch.empty(n_bytes, dtype=torch.uint8, device=dev)
     cbuf_b = torch.empty(n_bytes, dtype=torch.uint8, device=dev)
     cbuf_a.fill_(1)
@@ -621,12 +972,18 @@ def main() -> int:
         else:
             traffic_note = "counters taken on other kernel sources: stale"
 
+    del data, ws8, ws16, recs, calls
+    torch.cuda.empty_cache()
+
+    # ---------------------------------------------------------------- 1 MiB buffer
+    single = None
+    if not args.no_1mib:
+        single = bench_single_1mib(args, hu, wl, dev, stream)
+        torch.cuda.empty_cache()
+
     # ---------------------------------------------------------------- batched documents
     batched = None
-    texts = {p: data[p]["text"] for p in profiles}
     if not args.no_batched:
-        del data, ws8, ws16, recs
-        torch.cuda.empty_cache()
         batched = {"utf8_documents": bench_utf8_documents(args, hu, wl, dev, stream)}
         torch.cuda.empty_cache()
         batched["utf16_documents"] = bench_utf16_documents(args, hu, wl, dev, stream)
@@ -644,15 +1001,6 @@ def main() -> int:
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        cpu_bytes, cpu_t = 0, 0.0
-        for p in profiles:
-            t = texts[p]
-            t1 = time.perf_counter()
-            w, r = oracle.convert_utf8_to_utf16le(t.u8)
-            cpu_t += time.perf_counter() - t1
-            assert r.error == 0 and r.count == t.u16.size
-            cpu_bytes += t.u8.size + 2 * t.u16.size
         if sweep is not None:
             # the oracle on the same prefixes (up to 16 MiB): where the host catches up
             for size in SWEEP_SIZES:
@@ -664,9 +1012,20 @@ def main() -> int:
                 for _ in range(reps):
                     oracle.convert_utf8_to_utf16le(u8)
                 sweep[str(size)]["u8u16"]["cpu_oracle_us"] = round((time.perf_counter() - t1) / reps * 1e6, 2)
-        cpu = {"value": round(cpu_bytes / cpu_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+        head = cpu_legs["u8u16"]
+        cpu = {"value": round(head["bytes"] / head["s"] / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"validating UTF-8->UTF-16LE of the same {len(profiles)} x {args.size_mib} MiB profiles, "
-                         f"one pass each, single thread ({cpu_t:.1f} s)"}
+                         f"one pass each, single thread ({head['s']:.1f} s)",
+               "legs": {op: {"GBps": round(v["bytes"] / v["s"] / 1e9, 3),
+                             "Gchar_per_s": round(v["chars"] / v["s"] / 1e9, 3),
+                             "seconds": round(v["s"], 2), "threads": 1, "profiles": v["profiles"]}
+                        for op, v in cpu_legs.items() if v["s"] > 0},
+               **_cpu_info()}
+        if batched is not None:
+            cpu["utf8_documents"] = batched["utf8_documents"]["cpu_oracle"]
+            cpu["utf16_documents"] = batched["utf16_documents"]["cpu_oracle"]
+        if serving is not None and "oracle_latency" in serving:
+            cpu["serving_per_request"] = serving["oracle_latency"]
 
     out = {
         "metric": METRIC,
@@ -682,12 +1041,20 @@ def main() -> int:
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"large-buffer transcoding, {args.size_mib} MiB UTF-8 per profile",
-                   "profiles": profiles, "ops_per_step": ops, "parallelism": "single GPU"},
+                   "profiles": profiles, "ops_per_step": ops, "input_copies": copies,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": "hu::k_convert_u8<6, 2, false>", "traffic_note": traffic_note},
         "cpu_baseline": cpu,
         "copy_ceiling_GBps": round(copy_gbs, 1),
+        "oracle_agrees": {"large_buffers": oracle_checked,
+                          "single_1mib": single["oracle_agrees"] if single else None,
+                          "utf8_documents": batched["utf8_documents"]["oracle_agrees"] if batched else None,
+                          "utf16_documents": batched["utf16_documents"]["oracle_agrees"] if batched else None,
+                          "serving_requests": ({r: v["oracle_requests_checked"] for r, v in serving["rates"].items()}
+                                               if serving else None)},
+        "single_1mib": single,
         "batched": batched,
         "serving": serving,
         "size_sweep": sweep,

@@ -87,6 +87,10 @@ def _configure(lib):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, p, p, sz, p]
         f.restype = None
+    lib.oracle_many_at.argtypes = [ctypes.c_int, ctypes.c_int, p, p, sz, p]
+    lib.oracle_many_at.restype = None
+    lib.oracle_many_convert_at.argtypes = [ctypes.c_int, p, p, p, p, sz, p]
+    lib.oracle_many_convert_at.restype = None
     return lib
 
 
@@ -191,3 +195,36 @@ def many_validate_utf16le(buf, offsets):
 
 def many_utf8_length_from_utf16le(buf, offsets):
     return _many("oracle_many_utf16le", 1, _u16(buf), offsets, 2)
+
+
+def many_at(op: int, utf16: bool, src_addrs, n_units):
+    """Validation (op 0) or length (op 1) of inputs at host addresses
+    src_addrs[i] with n_units[i] code units each (the caller keeps the
+    buffers alive); returns (errors, counts) arrays."""
+    addrs = np.ascontiguousarray(src_addrs, dtype=np.uint64)
+    units = np.ascontiguousarray(n_units, dtype=np.uint64)
+    assert addrs.size == units.size
+    out = np.zeros(addrs.size, dtype=[("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
+    _load().oracle_many_at(op, 1 if utf16 else 0, _ptr(addrs), _ptr(units), addrs.size, _ptr(out))
+    return out["error"].copy(), out["count"].copy()
+
+
+def many_convert_at(utf16: bool, src_addrs, n_units, dst_addrs, dst_caps):
+    """Conversion of inputs at host addresses src_addrs[i] (n_units[i] code
+    units) into buffers at dst_addrs[i] holding dst_caps[i] output code
+    units (the caller owns and keeps alive every buffer); returns (errors,
+    counts) arrays. UTF-16LE -> UTF-8 if utf16, else UTF-8 -> UTF-16LE."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint64) for a in (src_addrs, n_units, dst_addrs, dst_caps)]
+    n = arrs[0].size
+    assert all(a.size == n for a in arrs)
+    out = np.zeros(n, dtype=[("error", "<i4"), ("reserved", "<i4"), ("count", "<u8")])
+    _load().oracle_many_convert_at(1 if utf16 else 0, *[_ptr(a) for a in arrs], n, _ptr(out))
+    return out["error"].copy(), out["count"].copy()
+
+
+def convert_raw(utf16: bool, src_addr: int, n_units: int, dst_addr: int, dst_cap: int) -> Result:
+    """One conversion on raw host addresses (the caller owns both buffers):
+    the least marshalling per call, for timing many small calls."""
+    lib = _load()
+    f = lib.oracle_convert_utf16le_to_utf8 if utf16 else lib.oracle_convert_utf8_to_utf16le
+    return _res(f(src_addr or None, n_units, dst_addr or None, dst_cap))

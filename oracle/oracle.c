@@ -304,3 +304,32 @@ void oracle_many_utf16le(int op, const uint8_t *src, const uint64_t *offsets,
         out[d] = op == 0 ? oracle_validate_utf16le(s, n) : oracle_utf8_length_from_utf16le(s, n);
     }
 }
+
+void oracle_many_at(int op, int utf16, const uint64_t *src, const uint64_t *n_units,
+                    size_t n, oracle_result *out)
+{
+    size_t i;
+    for (i = 0; i < n; i++) {
+        const uint8_t *s = (const uint8_t *)(uintptr_t)src[i];
+        size_t m = (size_t)n_units[i];
+        if (utf16)
+            out[i] = op == 0 ? oracle_validate_utf16le(s, m) : oracle_utf8_length_from_utf16le(s, m);
+        else
+            out[i] = op == 0 ? oracle_validate_utf8(s, m) : oracle_utf16_length_from_utf8(s, m);
+    }
+}
+
+void oracle_many_convert_at(int utf16, const uint64_t *src, const uint64_t *n_units,
+                            const uint64_t *dst, const uint64_t *dst_cap, size_t n,
+                            oracle_result *out)
+{
+    size_t i;
+    for (i = 0; i < n; i++) {
+        const uint8_t *s = (const uint8_t *)(uintptr_t)src[i];
+        uint8_t *d = (uint8_t *)(uintptr_t)dst[i];
+        if (utf16)
+            out[i] = oracle_convert_utf16le_to_utf8(s, (size_t)n_units[i], d, (size_t)dst_cap[i]);
+        else
+            out[i] = oracle_convert_utf8_to_utf16le(s, (size_t)n_units[i], d, (size_t)dst_cap[i]);
+    }
+}

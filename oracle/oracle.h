@@ -73,6 +73,16 @@ void oracle_many_utf8(int op, const uint8_t *src, const uint64_t *offsets,
                       size_t n_docs, oracle_result *out);
 void oracle_many_utf16le(int op, const uint8_t *src, const uint64_t *offsets,
                          size_t n_docs, oracle_result *out);
+/* The same over inputs anywhere in host memory: input i starts at address
+ * src[i] and holds n_units[i] code units; utf16 selects the encoding. */
+void oracle_many_at(int op, int utf16, const uint64_t *src, const uint64_t *n_units,
+                    size_t n, oracle_result *out);
+/* Conversion of many inputs: input i (address src[i], n_units[i] code units,
+ * UTF-16LE -> UTF-8 if utf16 else UTF-8 -> UTF-16LE) is converted into the
+ * buffer at address dst[i] of dst_cap[i] output code units. */
+void oracle_many_convert_at(int utf16, const uint64_t *src, const uint64_t *n_units,
+                            const uint64_t *dst, const uint64_t *dst_cap, size_t n,
+                            oracle_result *out);
 
 #ifdef __cplusplus
 }

@@ -296,3 +296,38 @@ def test_lengths_equal_converted_lengths_and_roundtrip():
         b, r = oracle.convert_utf16le_to_utf8(w)
         assert r == (oracle.OK, t.u8.size) and np.array_equal(b, t.u8)
         assert oracle.utf8_length_from_utf16le(w) == (oracle.OK, t.u8.size)
+
+
+def test_many_input_helpers_equal_single_calls():
+    """The batch helpers (inputs anywhere in host memory) return what the
+    single calls return, input by input, and convert into the given buffers."""
+    from paper_2109_10433_amd import workloads as wl
+    rng = np.random.default_rng(21)
+    text = wl.make_text("mix", 50_000, wl.rng_for("many-helpers"))
+    docs8, docs16 = [], []
+    for k in range(60):
+        a, b = sorted(int(x) for x in rng.integers(0, text.u8.size, 2))
+        d = text.u8[a:b].copy()
+        if k % 3 == 0 and d.size:
+            d[int(rng.integers(0, d.size))] = rng.choice([0x80, 0xC0, 0xED, 0xF8])
+        docs8.append(d)
+        a, b = sorted(int(x) for x in rng.integers(0, text.u16.size, 2))
+        w = text.u16[a:b].copy()
+        if k % 4 == 0 and w.size:
+            w[int(rng.integers(0, w.size))] = 0xDC00
+        docs16.append(w)
+    for utf16, docs, single in ((False, docs8, (oracle.validate_utf8, oracle.utf16_length_from_utf8)),
+                                (True, docs16, (oracle.validate_utf16le, oracle.utf8_length_from_utf16le))):
+        addrs = [d.ctypes.data for d in docs]
+        units = [d.size for d in docs]
+        for op in (0, 1):
+            errs, counts = oracle.many_at(op, utf16, addrs, units)
+            assert [tuple(single[op](d)) for d in docs] == list(zip(errs.tolist(), counts.tolist()))
+        caps = [3 * d.size if utf16 else d.size for d in docs]
+        outs = [np.full(max(c, 1), 0xEE, np.uint8 if utf16 else np.uint16) for c in caps]
+        errs, counts = oracle.many_convert_at(utf16, addrs, units, [o.ctypes.data for o in outs], caps)
+        for d, o, e, c in zip(docs, outs, errs, counts):
+            ref, r = (oracle.convert_utf16le_to_utf8 if utf16 else oracle.convert_utf8_to_utf16le)(d)
+            assert (int(e), int(c)) == tuple(r)
+            if r.error == 0:
+                assert np.array_equal(o[:r.count], ref)

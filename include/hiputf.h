@@ -76,9 +76,10 @@ enum {
 
 /* ------------------------------------------------------------------------
  * Synchronous calls. Each enqueues its kernels on `stream`, waits for that
- * stream, and returns the result. Scratch memory (128 bytes per tile; tiles
- * of 20 to 64 KiB of input depending on the operation, hu_workspace_bytes
- * gives the exact figure) comes from a per-device, per-stream cache owned by the library
+ * stream, and returns the result. Scratch memory (a 256-byte header, and for
+ * the conversions 128 bytes per tile of 20 or 24 KiB of input;
+ * hu_workspace_bytes gives the exact figure) comes from a per-device,
+ * per-stream cache owned by the library
  * (freed by hu_shutdown). n = 0 returns {HU_OK, 0}; pointers may then be NULL.
  * A NULL src (or dst with a non-zero capacity) with n > 0 is
  * HU_ERR_INVALID_ARGUMENT. On success exactly `count` units are written to
@@ -174,7 +175,9 @@ enum {
     HU_OP_CONVERT_UTF16LE_TO_UTF8 = 5
 };
 
-/* Workspace bytes for one call of `op` on n input code units. */
+/* Workspace bytes for one call of `op` on n input code units (validation and
+ * length need the 256-byte header only; a workspace shared by several
+ * operations is sized for the largest). */
 size_t hu_workspace_bytes(int op, size_t n_units);
 
 /* Input bytes per tile of the kernel that runs `op` (HU_OP_*) on n_units

@@ -5,11 +5,12 @@
 // every thread also needs the 4 bytes before and after its 16-byte chunk. The
 // direction policy (u8_dir.hpp / u16_dir.hpp) validates and counts each chunk.
 //
-//  - validate / length: tiles are taken grid-stride (the next tile's loads
-//    are issued before the current tile's work, so they are in flight
-//    meanwhile) and staged in LDS with the 16 bytes on either side; counts and
-//    the first flagged position are reduced per workgroup and added once at
-//    exit.
+//  - validate / length: no tile needs another's output offset, so every
+//    wave works alone on wave-tiles of a few 1 KiB pieces, grid-stride, with
+//    the next wave-tile's loads in flight while it analyses the current one;
+//    the wave-tile stays in registers (neighbouring dwords by DPP rotations);
+//    counts and the first flagged position are reduced per workgroup and
+//    added once at exit.
 //  - convert: one workgroup per tile, and the tile stays in registers from
 //    the load to the output: the neighbouring dwords come from the adjacent
 //    lanes (DPP) and, across wave and sub-tile boundaries, through a few LDS
@@ -27,8 +28,6 @@
 
 namespace hu {
 
-constexpr int kSubWords = kSub / 4;
-
 struct Doc {
     const uint8_t *base;          // 16-byte aligned address at or below the input
     unsigned long long off_b;     // first input byte, relative to base
@@ -38,12 +37,8 @@ struct Doc {
     unsigned long long cap;       // output capacity in code units
 };
 
-template <int U>
-constexpr int tile_words() { return 4 + U * kSubWords + 4; }
-
-template <class Dir, int U>
+template <class Dir>
 struct ScanShared {
-    alignas(16) unsigned int in[tile_words<U>()];
     alignas(16) unsigned char table[Dir::kNeedsTable ? 4096 : 16];
     unsigned long long red[kWaves];
     int flag;
@@ -80,12 +75,14 @@ __device__ __forceinline__ void build_pair_table(unsigned char *table)
 }
 
 // Issue all loads of tile `tile`: U chunks per thread, plus (thread 0) the
-// granules just before and just after the tile. Unmasked: stage_tile and
-// settle_tile zero what lies outside the document.
+// granules just before and just after the tile. Unmasked: settle_tile zeroes
+// what lies outside the document.
 template <int U>
 __device__ __forceinline__ void load_tile(const Doc &d, unsigned long long tile, uint4 q[U], uint4 &pre, uint4 &post)
 {
     const unsigned long long tv = tile * (unsigned long long)(U * kSub);
+    // guarded loads whatever the tile (an unguarded branch for tiles wholly
+    // inside the input measured 2-3 % slower here)
 #pragma unroll
     for (int u = 0; u < U; ++u)
         q[u] = load_granule_raw(d.base, tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
@@ -93,49 +90,6 @@ __device__ __forceinline__ void load_tile(const Doc &d, unsigned long long tile,
         pre = load_granule_raw(d.base, tv >= 16 ? tv - 16 : 0, d.off_b, d.end_b);
         post = load_granule_raw(d.base, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
     }
-}
-
-// Registers -> LDS: [16 bytes before | tile | 16 bytes after], with the bytes
-// outside the document zeroed (tiles that cover the document edges only).
-// SWAP: big-endian UTF-16 input, brought to little endian here.
-template <int U, bool SWAP = false>
-__device__ __forceinline__ void stage_tile(unsigned int *in, const Doc &d, unsigned long long tile, uint4 q[U],
-                                           uint4 pre, uint4 post)
-{
-    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
-    if (tv < d.off_b || tv + (unsigned long long)U * kSub > d.end_b) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            q[u] = mask_granule(q[u], tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
-    }
-    if constexpr (SWAP) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            q[u] = swap16(q[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        *reinterpret_cast<uint4 *>(&in[4 + u * kSubWords + 4 * threadIdx.x]) = q[u];
-    if (threadIdx.x == 0) {
-        pre = tv >= 16 ? mask_granule(pre, tv - 16, d.off_b, d.end_b) : make_uint4(0, 0, 0, 0);
-        post = mask_granule(post, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
-        if constexpr (SWAP) {
-            pre = swap16(pre);
-            post = swap16(post);
-        }
-        *reinterpret_cast<uint4 *>(&in[0]) = pre;
-        *reinterpret_cast<uint4 *>(&in[4 + U * kSubWords]) = post;
-    }
-}
-
-// This thread's chunk of sub-tile u with the 4 bytes on each side.
-__device__ __forceinline__ void read_chunk(const unsigned int *in, int u, unsigned int x[6])
-{
-    const int b = 4 + u * kSubWords + 4 * threadIdx.x;
-    const uint4 v = *reinterpret_cast<const uint4 *>(&in[b]);
-    x[0] = in[b - 1];
-    x[1] = v.x; x[2] = v.y; x[3] = v.z; x[4] = v.w;
-    x[5] = in[b + 4];
 }
 
 // A tile held in registers: this thread's chunk of every sub-tile. The
@@ -333,48 +287,6 @@ __device__ __forceinline__ void count_tile(const TileRegs<U> &t, const Doc &d, u
     }
 }
 
-// Validation (and counting) of a staged tile for the validate / length
-// kernels: one sub-tile at a time in a rolled loop (the convert kernel keeps
-// the per-sub-tile counts and unrolls; here only their sum matters, and a
-// rolled loop keeps one sub-tile's values live at a time). Edge tiles: as in
-// analyze_tile.
-template <class Dir, int U, bool COUNT>
-__device__ __forceinline__ void scan_tile(const unsigned int *in, const unsigned char *table, const Doc &d,
-                                          unsigned long long tile, unsigned long long &total,
-                                          unsigned long long &flag_min)
-{
-    const unsigned long long tv = tile * (unsigned long long)(U * kSub);
-    const bool interior = tile_is_interior<U>(d, tile);
-    unsigned int sum = 0;
-#pragma unroll 1
-    for (int u = 0; u < U; ++u) {
-        unsigned int x[6];
-        read_chunk(in, u, x);
-        const unsigned long long cv = tv + (unsigned long long)u * kSub + (unsigned long long)threadIdx.x * kChunk;
-        int f;
-        unsigned int cls;
-        unsigned int c = Dir::template analyze<COUNT>(x, table, &f, &cls);
-        if (f != kNoFlag) {
-            const unsigned long long pos = (cv - d.off_b) + (long long)f * Dir::kInUnit;
-            flag_min = pos < flag_min ? pos : flag_min;
-        }
-        if (COUNT && !interior) {
-            unsigned int lo, hi;
-            chunk_range<Dir>(d, cv, lo, hi);
-            c -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
-        }
-        sum += c;
-    }
-    if (COUNT)
-        total += sum;
-    if (!interior) {
-        end_check<Dir, U>(d, tile, flag_min);
-        const unsigned long long n_b = d.end_b - d.off_b;
-        if (flag_min != ~0ull && flag_min >= n_b)
-            flag_min = n_b - Dir::kInUnit;
-    }
-}
-
 // Exclusive offsets of every thread's count for each of U sub-tiles, and the
 // sub-tile totals, with one barrier. Counts are at most 32 per thread, so two
 // sub-tiles share one 32-bit scan (a wave's total stays below 2^16). With
@@ -498,37 +410,197 @@ __device__ __forceinline__ void workgroup_exit(unsigned long long my_total, unsi
     const unsigned long long f = block_min_u64(my_flag, red);
     const unsigned long long t = add_total ? block_sum_u64(my_total, red) : 0ull;
     if (threadIdx.x == 0) {
+        // both atomics have returned before finish_launch counts the
+        // workgroup done (relaxed, no cache-wide fence: see finish_launch)
         if (f != ~0ull)
-            atomicMax(&hdr->err_key, ~f);
-        if (add_total && t != 0)
-            atomicAdd(&hdr->total, t);
+            report_flag(&hdr->err_key, f);
+        if (add_total && t != 0) {
+            const unsigned long long old = atomicAdd(&hdr->total, t);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (old == 0x5A5A5A5A5A5A5A5Aull)   // consumes the returned value (forces the wait)
+                __builtin_amdgcn_s_sleep(1);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
     }
     finish_launch(c, hdr, status, status_cap, out, s_flag, &red[0]);
 }
 
 // ------------------------------------------------------------ validate / length
-template <class Dir, int MODE, int U, bool SWAP = false>
+// A wave-tile is P pieces of 1 KiB, a piece one 16-byte load per lane; wave w
+// of a grid of W waves takes wave-tiles w, w + W, w + 2W, ..., issues all
+// loads of one at once and analyses each piece as soon as its load is in
+// (the other waves of the SIMD keep memory busy meanwhile). A lane's
+// neighbouring dwords come from the adjacent lanes by DPP rotations:
+// lane 0's dword before from lane 63 of the piece before (of the same
+// register), lane 63's dword after from lane 0 of the piece after, and at the
+// wave-tile's two ends from one load of the same address in every lane.
+constexpr int kPiece = 64 * kChunk;
+
+template <int P>
+struct WaveTile {
+    uint4 q[P];
+    unsigned int pre, post;   // the dword just before the wave-tile, just after it
+};
+
+// The dword at byte position v (4-byte aligned, relative to the document's
+// 16-byte aligned base); a dword with no byte of the document is not read,
+// its load goes to the document's first dword instead (as load_granule_raw).
+__device__ __forceinline__ unsigned int load_dword_raw(const uint8_t *base, unsigned long long v, unsigned long long off,
+                                                       unsigned long long end)
+{
+    const bool any = v < end && v + 4 > off;
+    const unsigned long long a = any ? v : (off & ~3ull);
+    // a vector load although the address is uniform: a scalar load would share
+    // its wait counter with the LDS reads of the analysis, out of order, so
+    // every table lookup would wait for it
+    return *reinterpret_cast<const unsigned int *>(base + a + opaque(0u));
+}
+
+// Zero the bytes of dword w (at position v) that are outside [off, end).
+__device__ __forceinline__ unsigned int mask_dword(unsigned int w, unsigned long long v, unsigned long long off,
+                                                   unsigned long long end)
+{
+    const long long lo_s = (long long)off - (long long)v, hi_s = (long long)end - (long long)v;
+    const int lo = lo_s < 0 ? 0 : (lo_s > 4 ? 4 : (int)lo_s);
+    const int hi = hi_s < 0 ? 0 : (hi_s > 4 ? 4 : (int)hi_s);
+    const unsigned long long m = ((1ull << (8 * hi)) - 1) & ~((1ull << (8 * lo)) - 1);
+    return w & (unsigned int)m;
+}
+
+// Lane l receives lane l - 1's value, lane 0 lane 63's (DPP wave_ror:1).
+__device__ __forceinline__ unsigned int rotate_from_lower_lane(unsigned int v)
+{
+    return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xF, 0xF, false);
+}
+
+// Lane l receives lane l + 1's value, lane 63 lane 0's (DPP wave_rol:1).
+__device__ __forceinline__ unsigned int rotate_from_upper_lane(unsigned int v)
+{
+    return (unsigned int)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xF, 0xF, false);
+}
+
+// All loads of wave-tile wt, unmasked (scan_wave_tile zeroes what lies
+// outside the document).
+template <int P>
+__device__ __forceinline__ void load_wave_tile(const Doc &d, unsigned long long wt, WaveTile<P> &t)
+{
+    const unsigned int lane = threadIdx.x & 63;
+    const unsigned long long tv = wt * (unsigned long long)(P * kPiece);
+    if (tv >= d.off_b && tv + (unsigned long long)P * kPiece <= d.end_b) {
+        // every granule of the wave-tile holds bytes of the document: no guards
+        const uint4 *g = reinterpret_cast<const uint4 *>(d.base + tv) + lane;
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+            t.q[u] = g[u * 64];
+    } else {
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+            t.q[u] = load_granule_raw(d.base, tv + (unsigned long long)u * kPiece + lane * kChunk, d.off_b, d.end_b);
+    }
+    t.pre = load_dword_raw(d.base, tv >= 4 ? tv - 4 : 0, d.off_b, d.end_b);
+    t.post = load_dword_raw(d.base, tv + (unsigned long long)P * kPiece, d.off_b, d.end_b);
+}
+
+// Validation (and counting) of one wave-tile; all lanes of the wave call.
+// Tiles at the document's edges zero what lies outside it and correct their
+// counts as analyze_tile does; the wave-tile that holds the last input unit
+// checks for a last character cut short.
+template <class Dir, int P, bool COUNT, bool SWAP>
+__device__ __forceinline__ void scan_wave_tile(WaveTile<P> &t, const unsigned char *table, const Doc &d,
+                                               unsigned long long wt, unsigned long long &total,
+                                               unsigned long long &flag_min)
+{
+    const unsigned int lane = threadIdx.x & 63;
+    const unsigned long long tv = wt * (unsigned long long)(P * kPiece);
+    const bool interior = tv >= d.off_b && tv + (unsigned long long)P * kPiece < d.end_b;
+    // the dwords beyond the wave-tile are masked whatever the tile (the first
+    // wave-tile of a document that starts 16-byte aligned is interior, and has
+    // nothing before it)
+    const unsigned int pre = tv >= 4 ? mask_dword(t.pre, tv - 4, d.off_b, d.end_b) : 0u;
+    const unsigned int post = mask_dword(t.post, tv + (unsigned long long)P * kPiece, d.off_b, d.end_b);
+    if (!interior) {
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+            t.q[u] = mask_granule(t.q[u], tv + (unsigned long long)u * kPiece + lane * kChunk, d.off_b, d.end_b);
+    }
+    if constexpr (SWAP) {
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+            t.q[u] = swap16(t.q[u]);
+    }
+    unsigned int sum = 0;
+    unsigned int rel_min = ~0u;           // first flag, as a byte offset in the wave-tile
+    unsigned int before = SWAP ? swap16(pre) : pre;   // lane 0: the dword before the piece
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        unsigned int x[6];
+        x[1] = t.q[u].x; x[2] = t.q[u].y; x[3] = t.q[u].z; x[4] = t.q[u].w;
+        const unsigned int r = rotate_from_lower_lane(x[4]);
+        x[0] = lane == 0 ? before : r;
+        before = r;                       // at lane 0: lane 63's last dword, the next piece's dword before
+        const unsigned int after = u + 1 < P ? rotate_from_upper_lane(t.q[u + 1 < P ? u + 1 : u].x)
+                                             : (SWAP ? swap16(post) : post);
+        const unsigned int l = rotate_from_upper_lane(x[1]);
+        x[5] = lane == 63 ? after : l;
+        int f;
+        unsigned int cls;
+        const unsigned int c = Dir::template analyze<COUNT>(x, table, &f, &cls);
+        if (f != kNoFlag) {
+            const unsigned int rel = (unsigned int)(u * kPiece) + lane * kChunk + (unsigned int)f * Dir::kInUnit;
+            rel_min = rel < rel_min ? rel : rel_min;
+        }
+        sum += c;
+        // keep pieces from being interleaved by the scheduler (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (COUNT) {
+        total += sum;
+        if (!interior && lane == 0) {
+            // each zero outside the input counted as one unit (a byte or word
+            // below 0x80): the wave-tile's units outside it, taken off once
+            const unsigned long long te = tv + (unsigned long long)P * kPiece;
+            const unsigned long long lo = tv > d.off_b ? tv : d.off_b, hi = te < d.end_b ? te : d.end_b;
+            const unsigned long long inside = hi > lo ? (hi - lo) / Dir::kInUnit : 0ull;
+            total -= (unsigned long long)(P * kPiece / Dir::kInUnit) - inside;
+        }
+    }
+    if (rel_min != ~0u) {
+        // zeros before the input are never flagged: the position is >= off_b
+        const unsigned long long pos = tv + rel_min - d.off_b;
+        flag_min = pos < flag_min ? pos : flag_min;
+    }
+    if (!interior) {
+        if (lane == 0 && d.end_b > tv && d.end_b <= tv + (unsigned long long)P * kPiece) {
+            const long long j = Dir::end_truncation(d.base, d.off_b, d.end_b);
+            if (j >= 0 && (unsigned long long)j < flag_min)
+                flag_min = (unsigned long long)j;
+        }
+        const unsigned long long n_b = d.end_b - d.off_b;
+        if (flag_min != ~0ull && flag_min >= n_b)
+            flag_min = n_b - Dir::kInUnit;
+    }
+}
+
+// n_tiles: wave-tiles of P pieces covering the document.
+template <class Dir, int MODE, int P, bool SWAP = false>
 __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_tiles, WsHeader *hdr,
                                                  unsigned long long *status, unsigned long long status_cap,
                                                  hu_result *out)
 {
-    __shared__ ScanShared<Dir, U> s;
+    __shared__ ScanShared<Dir> s;
     if (Dir::kNeedsTable)
         build_pair_table(s.table);
+    __syncthreads();
     unsigned long long my_total = 0, my_flag = ~0ull;
-    unsigned long long tile = blockIdx.x;
-    uint4 q[U], pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
-    if (tile < n_tiles)
-        load_tile<U>(d, tile, q, pre, post);
-    while (tile < n_tiles) {
-        stage_tile<U, SWAP>(s.in, d, tile, q, pre, post);
-        __syncthreads();
-        const unsigned long long next = tile + gridDim.x;
-        if (next < n_tiles)
-            load_tile<U>(d, next, q, pre, post);      // in flight during this tile's work
-        scan_tile<Dir, U, MODE == kLength>(s.in, s.table, d, tile, my_total, my_flag);
-        __syncthreads();
-        tile = next;
+    const unsigned long long stride = (unsigned long long)gridDim.x * kWaves;
+    // the wave's index, known to the compiler as uniform: the wave-tile
+    // index and everything derived from it stay in scalar registers
+    const unsigned int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned long long wt = (unsigned long long)blockIdx.x * kWaves + wave;
+    for (; wt < n_tiles; wt += stride) {
+        WaveTile<P> t;
+        load_wave_tile<P>(d, wt, t);
+        scan_wave_tile<Dir, P, MODE == kLength, SWAP>(t, s.table, d, wt, my_total, my_flag);
     }
     const CallInfo c{d.base + d.off_b, d.n, d.cap, MODE == kLength ? Dir::kOpLength : Dir::kOpValidate};
     workgroup_exit(my_total, my_flag, s.red, c, hdr, status, status_cap, out, &s.flag, MODE == kLength);

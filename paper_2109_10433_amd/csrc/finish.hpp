@@ -168,9 +168,14 @@ __device__ inline void finish_launch(const CallInfo &c, WsHeader *hdr, unsigned 
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        // release: this workgroup's error key / totals are complete before it
-        // counts itself done; acquire for the last one
-        const unsigned int prev = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // The workgroup's contributions (error key, totals) are device-scope
+        // atomics whose results it has already waited for, so they are
+        // performed before this count is; the last workgroup reads them with
+        // device-scope atomic loads after its own count has returned. Relaxed
+        // ordering: a release or acquire at device scope would write back or
+        // invalidate the whole L2 of the workgroup's XCD once per workgroup,
+        // which stalls every other workgroup's loads there.
+        const unsigned int prev = __hip_atomic_fetch_add(&hdr->done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         *s_flag = (prev == gridDim.x - 1) ? 1 : 0;
     }
     __syncthreads();

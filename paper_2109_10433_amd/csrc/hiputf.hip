@@ -69,14 +69,14 @@ KernelChoice choose_kernel(int op, unsigned long long n_bytes)
         return kc;
     }
     switch (op) {
-    case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kUValidate8>), (unsigned long long)kUValidate8 * kSub, false};
-    case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kULength8>), (unsigned long long)kULength8 * kSub, false};
+    case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kPValidate8>), kPValidate8 * kPieceBytes, false};
+    case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kPLength8>), kPLength8 * kPieceBytes, false};
     case HU_OP_CONVERT_UTF8_TO_UTF16LE:
         if (n_bytes < kSmallConvert8Bytes)
             return {HU_K(k_convert_u8<kUConvert8Small, kConvert>), (unsigned long long)kUConvert8Small * kSub, true};
         return {HU_K(k_convert_u8<kUConvert8, kConvert>), (unsigned long long)kUConvert8 * kSub, true};
-    case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kUValidate16>), (unsigned long long)kUValidate16 * kSub, false};
-    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kULength16>), (unsigned long long)kULength16 * kSub, false};
+    case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kPValidate16>), kPValidate16 * kPieceBytes, false};
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kPLength16>), kPLength16 * kPieceBytes, false};
     default: return {HU_K(k_convert_u16<kUConvert16, kConvert>), (unsigned long long)kUConvert16 * kSub, true};
     }
 #undef HU_K
@@ -89,6 +89,17 @@ unsigned long long tiles_for(int op, const void *src, unsigned long long n_units
     const unsigned long long off = (unsigned long long)((uintptr_t)src & 15u);
     const unsigned long long tb = choose_kernel(op, bytes).tile_bytes;
     return (off + bytes + tb - 1) / tb;
+}
+
+// Workspace bytes a call needs: the header, and for the convert kernels one
+// status word (on its own 128-byte line) per tile.
+unsigned long long workspace_need(int op, const void *src, unsigned long long n_units)
+{
+    const bool u16 = (op & ~kOpFlags) >= HU_OP_VALIDATE_UTF16LE;
+    const unsigned long long bytes = u16 ? 2 * n_units : n_units;
+    if (n_units == 0 || !choose_kernel(op, bytes).one_group_per_tile)
+        return kHeaderBytes;
+    return kHeaderBytes + 8ull * kStatusStride * tiles_for(op, src, n_units);
 }
 
 // op: HU_OP_* with the flags above (only on the combinations choose_kernel has)
@@ -112,7 +123,7 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     if (choose_kernel(op, n_bytes).fn == nullptr)
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned long long n_tiles = n ? tiles_for(op, src, n) : 0;
-    if (ws_bytes < kHeaderBytes + 8ull * kStatusStride * n_tiles)
+    if (ws_bytes < workspace_need(op, src, n))
         return HU_ERR_INVALID_ARGUMENT;
 
     WsHeader *hdr = reinterpret_cast<WsHeader *>(ws);
@@ -339,7 +350,7 @@ hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, uns
     if (slot == nullptr)
         return make_result(HU_ERR_DEVICE, 0);
     std::lock_guard<std::mutex> lk(slot->mu);
-    const size_t need = kHeaderBytes + 8ull * kStatusStride * tiles_for(op, src, n);
+    const size_t need = workspace_need(op, src, n);
     if (slot->d_result == nullptr) {
         if (hipMalloc((void **)&slot->d_result, 256) != hipSuccess ||
             hipHostMalloc((void **)&slot->h_result, sizeof(hu_result), hipHostMallocDefault) != hipSuccess) {
@@ -518,8 +529,12 @@ size_t hu_workspace_bytes(int op, size_t n_units)
         return 0;
     // worst case over source alignments: 15 bytes of offset
     const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
-    // the smallest tile the operation may take: enough for any smaller input too
-    const unsigned long long tb = hu::choose_kernel(op, 0).tile_bytes;
+    // the smallest tile the operation may take: enough for any smaller input
+    // too; validate / length keep no status words
+    const hu::KernelChoice kc = hu::choose_kernel(op, 0);
+    if (!kc.one_group_per_tile)
+        return hu::kHeaderBytes;
+    const unsigned long long tb = kc.tile_bytes;
     return hu::kHeaderBytes + 8ull * hu::kStatusStride * ((bytes + 15 + tb - 1) / tb);
 }
 

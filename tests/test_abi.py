@@ -65,12 +65,17 @@ def test_detect_bom_on_the_host():
 
 
 def test_tile_bytes_on_the_host():
-    """hu_tile_bytes is host-only: tile sizes per operation (4 KiB sub-tiles;
-    the UTF-8 -> UTF-16LE conversion takes larger tiles from 64 MiB on), 0
-    for an unknown op."""
+    """hu_tile_bytes is host-only: tile sizes per operation (conversions: 4 KiB
+    sub-tiles per workgroup tile, the UTF-8 -> UTF-16LE conversion taking
+    larger tiles from 64 MiB on; validation and length: 1 KiB pieces per wave
+    tile), 0 for an unknown op; the workspace of validation and length is the
+    header alone."""
     from paper_2109_10433_amd import binding as hu
-    sub = 4096
-    want = {0: 12 * sub, 1: 10 * sub, 2: 5 * sub, 3: 16 * sub, 4: 10 * sub, 5: 6 * sub}
+    sub, piece = 4096, 1024
+    want = {0: 4 * piece, 1: 4 * piece, 2: 5 * sub, 3: 4 * piece, 4: 4 * piece, 5: 6 * sub}
+    for op in (0, 1, 3, 4):
+        assert hu.lib.hu_workspace_bytes(op, 1 << 28) == 256
+    assert hu.lib.hu_workspace_bytes(2, 1 << 20) == 256 + 128 * ((((1 << 20) + 15) + 5 * sub - 1) // (5 * sub))
     for op, tb in want.items():
         assert hu.lib.hu_tile_bytes(op, 1000) == tb
     assert hu.lib.hu_tile_bytes(2, (64 << 20) - 1) == 5 * sub

@@ -342,9 +342,19 @@ def test_async_workspace_reuse():
         assert r == tuple(orr)
         if r.error == 0:
             assert np.array_equal(dst.cpu().numpy().view(np.uint16)[:r.count], ow)
-    say("async validate with too-small workspace")
-    rc = hu.lib.validate_utf8_async(src.data_ptr(), src.numel(), rec.data_ptr(), wp, 256, hu.stream_handle())
+    say("async calls with too-small workspaces")
+    # validation needs the 256-byte header only, conversion also status words
+    rc = hu.lib.validate_utf8_async(src.data_ptr(), src.numel(), rec.data_ptr(), wp, 128, hu.stream_handle())
     assert rc == hu.INVALID_ARGUMENT
+    dst = torch.zeros(src.numel(), dtype=torch.int16, device="cuda")
+    rc = hu.lib.convert_utf8_to_utf16le_async(src.data_ptr(), src.numel(), dst.data_ptr(), src.numel(),
+                                              rec.data_ptr(), wp, 256, hu.stream_handle())
+    assert rc == hu.INVALID_ARGUMENT
+    assert hu.lib.hu_workspace_bytes(hu.OP_VALIDATE_UTF8, src.numel()) == 256
+    rc = hu.lib.validate_utf8_async(src.data_ptr(), src.numel(), rec.data_ptr(), wp, 256, hu.stream_handle())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert hu.result_from_device(rec) == tuple(oracle.validate_utf8(text.u8))
 
 
 def test_repeat_determinism():

@@ -92,7 +92,10 @@ enum {
 /* UTF-8 well-formedness (section 3, six rules). */
 hu_result validate_utf8(const uint8_t *src, size_t n_bytes, void *stream);
 
-/* Number of UTF-16 words the UTF-8 input converts to (validates first). */
+/* Number of UTF-16 words the UTF-8 input converts to (validates first): one
+ * word per character of one to three bytes, two for a four-byte character
+ * (Table "utfsummary", section 3: code point ranges and their UTF-8 and
+ * UTF-16 lengths). On invalid input, the error of validate_utf8. */
 hu_result utf16_length_from_utf8(const uint8_t *src, size_t n_bytes, void *stream);
 
 /* Validating UTF-8 -> UTF-16LE (section 4). dst holds dst_cap_words words;
@@ -103,7 +106,10 @@ hu_result convert_utf8_to_utf16le(const uint8_t *src, size_t n_bytes,
 /* UTF-16LE well-formedness (section 3, surrogate pairing). src: n_words words. */
 hu_result validate_utf16le(const uint16_t *src, size_t n_words, void *stream);
 
-/* Number of UTF-8 bytes the UTF-16LE input converts to (validates first). */
+/* Number of UTF-8 bytes the UTF-16LE input converts to (validates first):
+ * one byte for a word below U+0080, two below U+0800, three for any other
+ * word outside the surrogates, four for a surrogate pair (Table "utfsummary",
+ * section 3). On invalid input, the error of validate_utf16le. */
 hu_result utf8_length_from_utf16le(const uint16_t *src, size_t n_words, void *stream);
 
 /* Validating UTF-16LE -> UTF-8 (section 5). dst holds dst_cap_bytes bytes;

@@ -2,21 +2,20 @@
 //
 // Three steps, all on the device (nothing is read back, so a call can be
 // recorded into a HIP graph and replayed with new document tables):
-//   plan: one workgroup gives every document its tiles (work items): a scan
-//         over the documents' tile counts, UTF-8 documents first, then
-//         UTF-16 ones; documents with no input or invalid arguments get their
-//         result here. It also advances the workspace epoch.
+//   plan: every document gets its work: none (empty, or invalid arguments:
+//         its result is written here), one small-document item (all its
+//         bytes fit one wave's tile of four 1 KiB pieces), or tiles (work
+//         items of U sub-tiles of 4 KiB). Items are numbered UTF-8 tiles
+//         first, then UTF-16 tiles, then small documents, each in document
+//         order. The plan also advances the workspace epoch.
 //   fill: item -> (document, tile of the document) map.
-//   run:  one fused kernel for both input encodings, one workgroup per work
-//         item (workgroup b runs item base + b; the grids cover the host's
-//         upper bound on the item count, in as many launches as the grid size
-//         limit needs, and surplus workgroups leave at once). An item only
-//         waits (look-back) for earlier items of its own document, and
-//         workgroups are dispatched in id order, so the lowest unfinished
-//         item always has a running workgroup whose predecessors are done,
-//         however few workgroups the hardware holds at a time. Each document
-//         has its own look-back chain and error key; the workgroup that runs
-//         a document's last tile writes its result.
+//   run:  one fused kernel for both input encodings: one workgroup per tile
+//         item, in item order, then one wave per small document. A tile
+//         waits (look-back) only for earlier tiles of its own document; a
+//         small document is done by its wave alone (validate, count, wave
+//         scan, decode, store: no look-back, no barrier). Each document has
+//         its own look-back chain and error key; the workgroup that runs a
+//         document's last tile writes its result.
 #pragma once
 
 #include "engine.hpp"
@@ -31,21 +30,21 @@ static_assert(sizeof(BatchDoc) == sizeof(hu_doc), "hu_doc layout");
 
 // Workspace of a batch call:
 //   [BatchHeader (256 B) | status, item_cap words | first_item | err | item_map
-//    | two words per block of documents (planning)]
+//    | three words per block of documents (planning)]
 // The status array starts at a fixed offset; everything after it moves with
 // the call's shape (document count, item capacity). Status words must never
 // hold anything but status words or zeros, so memory that earlier calls used
 // for the per-document arrays is cleared before it becomes status words.
 struct BatchHeader {
-    unsigned long long items8;        // UTF-8 work items of this call
-    unsigned long long items16;       // UTF-16 work items
+    unsigned long long items8;        // UTF-8 tile items of this call
+    unsigned long long items16;       // UTF-16 tile items
+    unsigned long long smalls;        // small-document items
     unsigned long long dirty_from;    // 1 + first status word that may hold other data (0: none)
     unsigned long long clear_lo;      // status words [clear_lo, clear_hi) to clear in this call
     unsigned long long clear_hi;
     unsigned int epoch;               // tag of this call's status words
     unsigned int hang;                // set if a bounded wait gave up
     unsigned long long overflow;      // 1 if the call's items exceed the item capacity
-    unsigned long long pad;
 };
 static_assert(sizeof(BatchHeader) <= kHeaderBytes, "batch header size");
 
@@ -54,10 +53,17 @@ struct BatchWs {
     unsigned int *first_item;         // per document
     unsigned long long *err;          // per document error key
     unsigned long long *item_map;     // per item: document index | tile index << 32
-    unsigned long long *status;       // per item look-back status
-    unsigned long long *block;        // per block of documents: UTF-8, UTF-16 items (then their offsets)
+    unsigned long long *status;       // per tile item look-back status
+    unsigned long long *block;        // per block of documents: UTF-8, UTF-16, small items (then their offsets)
     unsigned long long item_cap;
 };
+
+constexpr unsigned int kNoItem = 0xFFFFFFFFu;
+
+// Small documents: all bytes (with the offset in the first 16-byte granule)
+// within one wave-tile of kSmallPieces pieces.
+constexpr int kSmallPieces = 4;
+constexpr unsigned long long kSmallDocBytes = (unsigned long long)kSmallPieces * kPiece;
 
 __device__ __forceinline__ bool op_is_u16(unsigned int op) { return op >= HU_OP_VALIDATE_UTF16LE; }
 __device__ __forceinline__ int op_mode(unsigned int op) { return (int)(op % 3u); }   // kValidate/kLength/kConvert
@@ -95,51 +101,66 @@ __device__ __forceinline__ int doc_check(const BatchDoc &b, const uint8_t *src_b
     return 0;
 }
 
+// Input bytes of a document counted from its 16-byte aligned base.
+__device__ __forceinline__ unsigned long long doc_span(const BatchDoc &b, const uint8_t *src_base)
+{
+    const unsigned long long off = (unsigned long long)((uintptr_t)(src_base + b.src_off) & 15u);
+    return off + (op_is_u16(b.op) ? 2 * b.n_units : b.n_units);
+}
+
+__device__ __forceinline__ bool doc_is_small(const BatchDoc &b, const uint8_t *src_base)
+{
+    return b.n_units > 0 && doc_span(b, src_base) <= kSmallDocBytes;
+}
+
+// Tile items of a document (0 for an empty or small one).
 __device__ __forceinline__ unsigned long long doc_tiles(const BatchDoc &b, const uint8_t *src_base,
                                                         unsigned long long tile_bytes)
 {
-    if (b.n_units == 0)
+    if (b.n_units == 0 || doc_is_small(b, src_base))
         return 0;
-    const unsigned long long off = (unsigned long long)((uintptr_t)(src_base + b.src_off) & 15u);
-    const unsigned long long bytes = op_is_u16(b.op) ? 2 * b.n_units : b.n_units;
-    return (off + bytes + tile_bytes - 1) / tile_bytes;
+    return (doc_span(b, src_base) + tile_bytes - 1) / tile_bytes;
 }
 
 constexpr int kPlanBlock = 1024;
+constexpr int kCounts = 3;   // UTF-8 tiles, UTF-16 tiles, small documents
 
-// Exclusive prefix over a 1024-thread workgroup of two counters at once.
-__device__ __forceinline__ void plan_scan2(unsigned long long a, unsigned long long b, unsigned long long *ea,
-                                           unsigned long long *eb, unsigned long long *ta, unsigned long long *tb,
-                                           unsigned long long (*s_tmp)[kPlanBlock / 64])
+// Exclusive prefix over a 1024-thread workgroup of three counters at once;
+// t[] receives the workgroup's totals.
+__device__ __forceinline__ void plan_scan(const unsigned long long v[kCounts], unsigned long long e[kCounts],
+                                          unsigned long long t[kCounts],
+                                          unsigned long long (*s_tmp)[kPlanBlock / 64])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    unsigned long long ia = a, ib = b;
+    unsigned long long inc[kCounts];
+#pragma unroll
+    for (int c = 0; c < kCounts; ++c)
+        inc[c] = v[c];
     for (int d = 1; d < 64; d <<= 1) {
-        const unsigned long long ua = __shfl_up(ia, d, 64), ub = __shfl_up(ib, d, 64);
-        if (lane >= d) {
-            ia += ua;
-            ib += ub;
+#pragma unroll
+        for (int c = 0; c < kCounts; ++c) {
+            const unsigned long long u = __shfl_up(inc[c], d, 64);
+            if (lane >= d)
+                inc[c] += u;
         }
     }
     if (lane == 63) {
-        s_tmp[0][wave] = ia;
-        s_tmp[1][wave] = ib;
+#pragma unroll
+        for (int c = 0; c < kCounts; ++c)
+            s_tmp[c][wave] = inc[c];
     }
     __syncthreads();
-    unsigned long long pa = 0, pb = 0, sa = 0, sb = 0;
-    for (int w = 0; w < kPlanBlock / 64; ++w) {
-        const unsigned long long xa = s_tmp[0][w], xb = s_tmp[1][w];
-        if (w < wave) {
-            pa += xa;
-            pb += xb;
+#pragma unroll
+    for (int c = 0; c < kCounts; ++c) {
+        unsigned long long before = 0, all = 0;
+        for (int w = 0; w < kPlanBlock / 64; ++w) {
+            const unsigned long long x = s_tmp[c][w];
+            before += w < wave ? x : 0ull;
+            all += x;
         }
-        sa += xa;
-        sb += xb;
+        e[c] = before + inc[c] - v[c];
+        t[c] = all;
     }
-    *ea = pa + ia - a;
-    *eb = pb + ib - b;
-    *ta = sa;
-    *tb = sb;
     __syncthreads();
 }
 
@@ -147,51 +168,50 @@ __device__ __forceinline__ void plan_scan2(unsigned long long a, unsigned long l
 // documents: blocks of kPlanBlock documents (one per thread, coalesced) sum
 // their work items; one workgroup turns the block sums into block offsets
 // and does the call's bookkeeping; the blocks then give every document its
-// first item. Items are numbered UTF-8 documents first, then UTF-16 ones,
-// each in document order.
+// first item.
 
-// Work items of document d (0 if it has none or fails the argument checks,
-// whose result goes to *err).
-__device__ __forceinline__ unsigned long long doc_items(const BatchDoc &b, const uint8_t *src_base,
-                                                        const uint8_t *dst_base, unsigned long long tile_bytes, int *err)
+// Work of document d: its three counts (at most one non-zero) and, when it
+// fails the argument checks, the error of its result.
+__device__ __forceinline__ void doc_work(const BatchDoc &b, const uint8_t *src_base, const uint8_t *dst_base,
+                                         unsigned long long tile_bytes, int *err, unsigned long long v[kCounts])
 {
+    v[0] = v[1] = v[2] = 0;
     *err = doc_check(b, src_base, dst_base);
-    return *err ? 0ull : doc_tiles(b, src_base, tile_bytes);
+    if (*err != 0 || b.n_units == 0)
+        return;
+    if (doc_is_small(b, src_base))
+        v[2] = 1;
+    else
+        v[op_is_u16(b.op) ? 1 : 0] = doc_tiles(b, src_base, tile_bytes);
 }
 
 __global__ __launch_bounds__(kPlanBlock) void k_batch_count(const BatchDoc *docs, unsigned int n_docs,
                                                             const uint8_t *src_base, const uint8_t *dst_base, BatchWs w,
                                                             unsigned long long tile_bytes)
 {
-    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ unsigned long long s_tmp[kCounts][kPlanBlock / 64];
     const unsigned long long d = (unsigned long long)blockIdx.x * kPlanBlock + threadIdx.x;
-    unsigned long long c8 = 0, c16 = 0;
+    unsigned long long v[kCounts] = {0, 0, 0};
     if (d < n_docs) {
-        const BatchDoc b = docs[d];
         int err;
-        const unsigned long long t = doc_items(b, src_base, dst_base, tile_bytes, &err);
-        if (op_is_u16(b.op))
-            c16 = t;
-        else
-            c8 = t;
+        doc_work(docs[d], src_base, dst_base, tile_bytes, &err, v);
     }
-    unsigned long long e8, e16, t8, t16;
-    plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);
-    if (threadIdx.x == 0) {
-        w.block[2 * blockIdx.x] = t8;
-        w.block[2 * blockIdx.x + 1] = t16;
-    }
+    unsigned long long e[kCounts], t[kCounts];
+    plan_scan(v, e, t, s_tmp);
+    if (threadIdx.x < kCounts)
+        w.block[kCounts * blockIdx.x + threadIdx.x] = t[threadIdx.x];
 }
 
-// The call's totals, the capacity check and the epoch in the header; status
-// words cleared when the epoch wraps. All threads of the workgroup call it.
-__device__ __forceinline__ void plan_bookkeeping(const BatchWs &w, unsigned long long t8, unsigned long long t16,
-                                                 int *s_wrap)
+// The call's totals, the capacity check and the epoch in
+// the header; status words cleared when the epoch wraps. All threads of the
+// workgroup call it.
+__device__ __forceinline__ void plan_bookkeeping(const BatchWs &w, const unsigned long long t[kCounts], int *s_wrap)
 {
-    const bool overflow = t8 + t16 > w.item_cap;
+    const bool overflow = t[0] + t[1] + t[2] > w.item_cap;
     if (threadIdx.x == 0) {
-        w.hdr->items8 = overflow ? 0 : t8;
-        w.hdr->items16 = overflow ? 0 : t16;
+        w.hdr->items8 = overflow ? 0 : t[0];
+        w.hdr->items16 = overflow ? 0 : t[1];
+        w.hdr->smalls = overflow ? 0 : t[2];
         w.hdr->overflow = overflow ? 1u : 0u;
         w.hdr->hang = 0;
         // status words of earlier calls' per-document arrays: cleared by fill
@@ -212,42 +232,60 @@ __device__ __forceinline__ void plan_bookkeeping(const BatchWs &w, unsigned long
 
 __global__ __launch_bounds__(kPlanBlock) void k_batch_plan(unsigned int n_blocks, BatchWs w)
 {
-    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ unsigned long long s_tmp[kCounts][kPlanBlock / 64];
     __shared__ int s_wrap;
-    unsigned long long t8 = 0, t16 = 0;   // items of the blocks so far
+    unsigned long long run[kCounts] = {0, 0, 0};   // items of the blocks so far
     for (unsigned int g0 = 0; g0 < n_blocks; g0 += kPlanBlock) {
         const unsigned int g = g0 + threadIdx.x;
-        const unsigned long long a = g < n_blocks ? w.block[2 * g] : 0ull;
-        const unsigned long long b = g < n_blocks ? w.block[2 * g + 1] : 0ull;
-        unsigned long long ea, eb, ta, tb;
-        plan_scan2(a, b, &ea, &eb, &ta, &tb, s_tmp);
+        unsigned long long v[kCounts], e[kCounts], t[kCounts];
+#pragma unroll
+        for (int c = 0; c < kCounts; ++c)
+            v[c] = g < n_blocks ? w.block[kCounts * g + c] : 0ull;
+        plan_scan(v, e, t, s_tmp);
         if (g < n_blocks) {
-            w.block[2 * g] = t8 + ea;          // block offsets, in place of the sums
-            w.block[2 * g + 1] = t16 + eb;
+#pragma unroll
+            for (int c = 0; c < kCounts; ++c)
+                w.block[kCounts * g + c] = run[c] + e[c];   // block offsets, in place of the sums
         }
-        t8 += ta;
-        t16 += tb;
+#pragma unroll
+        for (int c = 0; c < kCounts; ++c)
+            run[c] += t[c];
     }
-    plan_bookkeeping(w, t8, t16, &s_wrap);
+    plan_bookkeeping(w, run, &s_wrap);
 }
 
 // Document d's first work item, or its result if it has no work (error,
 // empty, or the call's items exceed the workspace's capacity).
 __device__ __forceinline__ void assign_doc(const BatchWs &w, hu_result *results, unsigned long long d, int err,
-                                           unsigned long long items, bool overflow, unsigned long long first)
+                                           const unsigned long long v[kCounts], bool overflow,
+                                           unsigned long long first)
 {
     if (err == 0 && overflow)
         err = HU_ERR_INVALID_ARGUMENT;   // work-item capacity of the workspace exceeded
-    if (err != 0 || items == 0) {
+    if (err != 0 || v[0] + v[1] + v[2] == 0) {
         hu_result r;
         r.error = err;
         r.reserved = 0;
         r.count = 0;
         results[d] = r;
-        w.first_item[d] = 0xFFFFFFFFu;
+        w.first_item[d] = kNoItem;
         return;
     }
     w.first_item[d] = (unsigned int)first;
+}
+
+// First item of a document from its category's offset before its block (o8,
+// o16, os), its exclusive offset inside the block and the call's totals.
+__device__ __forceinline__ unsigned long long first_item_of(const unsigned long long v[kCounts],
+                                                            const unsigned long long block_off[kCounts],
+                                                            const unsigned long long e[kCounts],
+                                                            unsigned long long items8, unsigned long long items16)
+{
+    if (v[2] != 0)
+        return items8 + items16 + block_off[2] + e[2];
+    if (v[1] != 0)
+        return items8 + block_off[1] + e[1];
+    return block_off[0] + e[0];
 }
 
 __global__ __launch_bounds__(kPlanBlock) void k_batch_assign(const BatchDoc *docs, unsigned int n_docs,
@@ -255,25 +293,21 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_assign(const BatchDoc *doc
                                                              hu_result *results, BatchWs w,
                                                              unsigned long long tile_bytes)
 {
-    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ unsigned long long s_tmp[kCounts][kPlanBlock / 64];
     const unsigned long long d = (unsigned long long)blockIdx.x * kPlanBlock + threadIdx.x;
-    unsigned long long c8 = 0, c16 = 0;
+    unsigned long long v[kCounts] = {0, 0, 0};
     int err = 0;
-    bool u16 = false;
-    if (d < n_docs) {
-        const BatchDoc b = docs[d];
-        u16 = op_is_u16(b.op);
-        const unsigned long long t = doc_items(b, src_base, dst_base, tile_bytes, &err);
-        if (u16)
-            c16 = t;
-        else
-            c8 = t;
-    }
-    unsigned long long e8, e16, t8, t16;
-    plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);   // every thread takes part
     if (d < n_docs)
-        assign_doc(w, results, d, err, c8 + c16, w.hdr->overflow != 0,
-                   u16 ? w.hdr->items8 + w.block[2 * blockIdx.x + 1] + e16 : w.block[2 * blockIdx.x] + e8);
+        doc_work(docs[d], src_base, dst_base, tile_bytes, &err, v);
+    unsigned long long e[kCounts], t[kCounts];
+    plan_scan(v, e, t, s_tmp);   // every thread takes part
+    if (d < n_docs) {
+        unsigned long long bo[kCounts];
+#pragma unroll
+        for (int c = 0; c < kCounts; ++c)
+            bo[c] = w.block[kCounts * blockIdx.x + c];
+        assign_doc(w, results, d, err, v, w.hdr->overflow != 0, first_item_of(v, bo, e, w.hdr->items8, w.hdr->items16));
+    }
 }
 
 // Planning of a call of at most kPlanBlock documents, all three steps in one
@@ -283,26 +317,20 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_plan1(const BatchDoc *docs
                                                             hu_result *results, BatchWs w,
                                                             unsigned long long tile_bytes)
 {
-    __shared__ unsigned long long s_tmp[2][kPlanBlock / 64];
+    __shared__ unsigned long long s_tmp[kCounts][kPlanBlock / 64];
     __shared__ int s_wrap;
     const unsigned int d = threadIdx.x;
-    unsigned long long c8 = 0, c16 = 0;
+    unsigned long long v[kCounts] = {0, 0, 0};
     int err = 0;
-    bool u16 = false;
-    if (d < n_docs) {
-        const BatchDoc b = docs[d];
-        u16 = op_is_u16(b.op);
-        const unsigned long long t = doc_items(b, src_base, dst_base, tile_bytes, &err);
-        if (u16)
-            c16 = t;
-        else
-            c8 = t;
-    }
-    unsigned long long e8, e16, t8, t16;
-    plan_scan2(c8, c16, &e8, &e16, &t8, &t16, s_tmp);
     if (d < n_docs)
-        assign_doc(w, results, d, err, c8 + c16, t8 + t16 > w.item_cap, u16 ? t8 + e16 : e8);
-    plan_bookkeeping(w, t8, t16, &s_wrap);
+        doc_work(docs[d], src_base, dst_base, tile_bytes, &err, v);
+    unsigned long long e[kCounts], t[kCounts];
+    plan_scan(v, e, t, s_tmp);
+    if (d < n_docs) {
+        const unsigned long long zero[kCounts] = {0, 0, 0};
+        assign_doc(w, results, d, err, v, t[0] + t[1] + t[2] > w.item_cap, first_item_of(v, zero, e, t[0], t[1]));
+    }
+    plan_bookkeeping(w, t, &s_wrap);
 }
 
 // item -> (document, tile) map; every error key back to zero; status words
@@ -317,22 +345,38 @@ __global__ void k_batch_fill(const BatchDoc *docs, unsigned int n_docs, const ui
     for (unsigned int d = blockIdx.x * blockDim.x + threadIdx.x; d < n_docs; d += gridDim.x * blockDim.x) {
         w.err[d] = 0;
         const unsigned int first = w.first_item[d];
-        if (first == 0xFFFFFFFFu)
+        if (first == kNoItem)
             continue;
-        const unsigned long long t = doc_tiles(docs[d], src_base, tile_bytes);
+        const BatchDoc b = docs[d];
+        const unsigned long long t = doc_tiles(b, src_base, tile_bytes);
+        if (t == 0) {
+            w.item_map[first] = (unsigned long long)d;   // a small document: one item
+            continue;
+        }
         for (unsigned long long k = 0; k < t; ++k)
             w.item_map[first + k] = (unsigned long long)d | (k << 32);
     }
 }
 
-// One work item (tile `tile` of document di, global item index i).
+// ------------------------------------------------------------ tile items
+// Everything chained_tile needs in LDS but the pair table (kept apart, shared
+// by every item and small document a workgroup does).
 template <class Dir, int U>
-__device__ __forceinline__ void batch_item(ConvertShared<Dir, U> &s, const BatchDoc &b, unsigned int di,
-                                           unsigned long long tile, unsigned long long i, unsigned int epoch,
-                                           const uint8_t *src_base, uint8_t *dst_base, hu_result *results, BatchWs w)
+struct BatchTileShared {
+    alignas(16) typename Dir::Out out[kStageFront + Dir::kStageUnits];
+    TileEdges<U> edges;
+    unsigned int scan[U][kWaves];
+    unsigned long long red[kWaves];
+    unsigned long long prefix;
+};
+
+// One tile item (tile `tile` of document di, global item index i).
+template <class Dir, int U>
+__device__ __forceinline__ void batch_item(BatchTileShared<Dir, U> &s, const unsigned char *table, const BatchDoc &b,
+                                           unsigned int di, unsigned long long tile, unsigned long long i,
+                                           unsigned int epoch, const uint8_t *src_base, uint8_t *dst_base,
+                                           hu_result *results, BatchWs w)
 {
-    if (Dir::kNeedsTable)
-        build_pair_table(s.table);
     const Doc d = make_doc(b, src_base, dst_base);
     const unsigned long long n_tiles = doc_tiles(b, src_base, (unsigned long long)U * kSub);
     const Chain cx{w.status, i - tile, i, epoch, &w.err[di], &w.hdr->hang, 1u};
@@ -344,39 +388,198 @@ __device__ __forceinline__ void batch_item(ConvertShared<Dir, U> &s, const Batch
         w.err[di] = 0;
     };
     switch (op_mode(b.op)) {
-    case kValidate: chained_tile<Dir, U, kValidate>(s, d, tile, n_tiles, cx, fin); break;
-    case kLength: chained_tile<Dir, U, kLength>(s, d, tile, n_tiles, cx, fin); break;
-    default: chained_tile<Dir, U, kConvert>(s, d, tile, n_tiles, cx, fin); break;
+    case kValidate: chained_tile<Dir, U, kValidate, false, false, true>(s, table, d, tile, n_tiles, cx, fin); break;
+    case kLength: chained_tile<Dir, U, kLength, false, false, true>(s, table, d, tile, n_tiles, cx, fin); break;
+    default: chained_tile<Dir, U, kConvert, false, false, true>(s, table, d, tile, n_tiles, cx, fin); break;
     }
 }
 
-template <int U>
-union BatchShared {
-    ConvertShared<U8Dir, U> u8;
-    ConvertShared<U16Dir, U> u16;
+// ------------------------------------------------------------ small documents
+// A wave's staging for one piece's output (either direction).
+union SmallStage {
+    alignas(16) unsigned short u8[kStageFront + U8Dir::kPieceStageUnits];
+    alignas(16) unsigned char u16[kStageFront + U16Dir::kPieceStageUnits];
 };
 
-// Items [0, n8) are UTF-8 input, [n8, n8 + n16) UTF-16LE. Dynamic LDS (unused)
-// may be requested at launch to cap the workgroups resident per CU.
+// This lane's chunk of piece u (below P) of a wave-tile, with the dword
+// before and after: DPP rotations across the wave, the neighbouring pieces at
+// lanes 0 and 63, zeros beyond the wave-tile.
+template <int P>
+__device__ __forceinline__ void piece_chunk(const WaveTile<P> &t, unsigned int u, unsigned int lane, unsigned int x[6])
+{
+    uint4 cur = t.q[0];
+    unsigned int prev_w = 0u, next_x = P > 1 ? t.q[P > 1 ? 1 : 0].x : 0u;
+#pragma unroll
+    for (int k = 1; k < P; ++k) {
+        if (u == (unsigned int)k) {
+            cur = t.q[k];
+            prev_w = t.q[k - 1].w;
+            next_x = k + 1 < P ? t.q[k + 1 < P ? k + 1 : k].x : 0u;
+        }
+    }
+    x[1] = cur.x; x[2] = cur.y; x[3] = cur.z; x[4] = cur.w;
+    const unsigned int r = rotate_from_lower_lane(x[4]);
+    const unsigned int before = rotate_from_lower_lane(prev_w);   // lane 0: lane 63's (zero for piece 0)
+    x[0] = lane == 0 ? before : r;
+    const unsigned int after = rotate_from_upper_lane(next_x);    // lane 63: lane 0's (zero after the last piece)
+    const unsigned int l = rotate_from_upper_lane(x[1]);
+    x[5] = lane == 63 ? after : l;
+}
+
+// One small document, by one whole wave (no barrier; the wave's own LDS
+// staging), piece by piece: validate and count the piece, offsets from a wave
+// scan, decode into the staging (shifted so that LDS and global addresses
+// agree modulo 16) and copy out. The first piece with a flag ends the work:
+// every piece before it was valid, so its smallest flag (or a last character
+// cut short by the end) is the document's first. A conversion may have
+// written the valid pieces before an error is found (the output of a failed
+// call is unspecified; nothing goes past the capacity). Lane 0 writes the
+// result.
+template <class Dir, int MODE>
+__device__ __forceinline__ void small_doc(typename Dir::Out *stage, const unsigned char *table, const Doc &d,
+                                          const CallInfo &call, hu_result *result)
+{
+    using Out = typename Dir::Out;
+    constexpr int P = kSmallPieces;
+    constexpr bool COUNT = MODE != kValidate;
+    constexpr unsigned int G = 16 / sizeof(Out);
+    const unsigned int lane = threadIdx.x & 63;
+    WaveTile<P> t;
+    load_wave_tile<P>(d, 0, t);
+#pragma unroll
+    for (int u = 0; u < P; ++u)
+        t.q[u] = mask_granule(t.q[u], (unsigned long long)u * kPiece + lane * kChunk, d.off_b, d.end_b);
+    const unsigned long long n_b = d.end_b - d.off_b;
+    const unsigned int n_pieces = (unsigned int)((d.end_b + kPiece - 1) / kPiece);
+    const unsigned int dst_mis = (unsigned int)(((uintptr_t)d.dst & 15u) / sizeof(Out));
+    Out *dst = reinterpret_cast<Out *>(d.dst);
+    // whether the output fits the capacity is known only at the end (the
+    // count of every piece): pieces are written as they come, each store
+    // guarded by the capacity (the output of a call that ends in
+    // OUTPUT_TOO_SMALL is unspecified)
+    constexpr bool emit_ok = MODE == kConvert;
+    unsigned long long total = 0, flag = ~0ull;
+#pragma unroll
+    for (unsigned int u = 0; u < P; ++u) {
+        if (u >= n_pieces)
+            break;
+        unsigned int x[6];
+        piece_chunk<P>(t, u, lane, x);
+        int f;
+        unsigned int cls;
+        unsigned int c = Dir::template analyze<COUNT>(x, table, &f, &cls);
+        cls = __builtin_amdgcn_readfirstlane(cls);
+        const unsigned long long cv = (unsigned long long)u * kPiece + lane * kChunk;
+        if (f != kNoFlag)
+            flag = cv + (unsigned long long)f * Dir::kInUnit - d.off_b;   // zeros before the input are never flagged
+        if (COUNT) {
+            unsigned int lo, hi;
+            chunk_range<Dir>(d, cv, lo, hi);
+            c -= (unsigned int)(kChunk / Dir::kInUnit) - (hi - lo);
+        }
+        if (u + 1 == n_pieces && lane == 0) {
+            const long long j = Dir::end_truncation(d.base, d.off_b, d.end_b);
+            if (j >= 0 && (unsigned long long)j < flag)
+                flag = (unsigned long long)j;
+        }
+        if (flag != ~0ull && flag >= n_b)
+            flag = n_b - Dir::kInUnit;   // zeros after a lead at the end: the last unit
+        flag = wave_min_u64(flag);
+        if (flag != ~0ull)
+            break;
+        if (COUNT) {
+            const unsigned int inc = wave_inclusive_sum(c);
+            const unsigned int tot = __builtin_amdgcn_readlane(inc, 63);
+            if (emit_ok && tot != 0) {
+                // zeros before the document in lane 0's first chunk land in the
+                // front margin (offsets counted from the buffer's start)
+                const unsigned int skip = (u == 0 && lane == 0) ? (unsigned int)(d.off_b / Dir::kInUnit) : 0u;
+                const unsigned int shift = (unsigned int)((dst_mis + total) % G);
+                Dir::emit(x, stage, kStageFront + shift + (inc - c) - skip, cls);
+                __builtin_amdgcn_wave_barrier();
+                copy_out<Dir, false, 64, Dir::kPieceStageUnits>(stage + kStageFront, shift, tot, dst,
+                                                                (long long)total - (long long)shift, d.cap, lane);
+                __builtin_amdgcn_wave_barrier();
+            }
+            total += tot;
+        }
+    }
+    if (lane == 0)
+        *result = result_from(call, flag != ~0ull ? ~flag : 0ull, 0u, total);
+}
+
+// Small document di, its operation's path.
+__device__ __forceinline__ void batch_small(SmallStage &stage, const unsigned char *table, const BatchDoc &b,
+                                            unsigned int di, const uint8_t *src_base, uint8_t *dst_base,
+                                            hu_result *results)
+{
+    const Doc d = make_doc(b, src_base, dst_base);
+    const CallInfo call{d.base + d.off_b, d.n, d.cap, (int)b.op};
+    hu_result *r = &results[di];
+    switch (b.op) {
+    case HU_OP_VALIDATE_UTF8: small_doc<U8Dir, kValidate>(stage.u8, table, d, call, r); break;
+    case HU_OP_UTF16_LENGTH_FROM_UTF8: small_doc<U8Dir, kLength>(stage.u8, table, d, call, r); break;
+    case HU_OP_CONVERT_UTF8_TO_UTF16LE: small_doc<U8Dir, kConvert>(stage.u8, table, d, call, r); break;
+    case HU_OP_VALIDATE_UTF16LE: small_doc<U16Dir, kValidate>(stage.u16, table, d, call, r); break;
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: small_doc<U16Dir, kLength>(stage.u16, table, d, call, r); break;
+    default: small_doc<U16Dir, kConvert>(stage.u16, table, d, call, r); break;
+    }
+}
+
+// ------------------------------------------------------------ run
+template <int U>
+struct BatchShared {
+    alignas(16) unsigned char table[4096];
+    union {
+        BatchTileShared<U8Dir, U> u8;
+        BatchTileShared<U16Dir, U> u16;
+        SmallStage small[kWaves];   // one per wave
+    } w;
+};
+
+// One fused launch over workgroups numbered base + blockIdx.x: the first nt
+// take the tile items in item order, the next ones four small documents each
+// (one per wave), and the rest (the host knows only upper bounds on both
+// counts) leave at once, before any work. Workgroups are dispatched in id
+// order, an item waits only for smaller items of its own document and a
+// small document for nothing, so the lowest unfinished item always has a
+// running workgroup whose predecessors are done, however few workgroups the
+// device holds at a time; the small documents, dispatched after the tiles,
+// fill the tail of the tile work. Dynamic LDS (unused) may be requested at
+// launch to cap the workgroups resident per CU.
 template <int U>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_batch_run(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_base, hu_result *results, BatchWs w,
-                 unsigned long long item_base)
+                 unsigned long long base)
 {
     __shared__ BatchShared<U> s;
-    const unsigned long long i = item_base + blockIdx.x;
-    const unsigned long long n8 = w.hdr->items8, n16 = w.hdr->items16;
-    if (i >= n8 + n16)
+    const unsigned long long g = base + blockIdx.x;
+    const unsigned long long n8 = w.hdr->items8, nt = n8 + w.hdr->items16, smalls = w.hdr->smalls;
+    if (g < nt) {
+        build_pair_table(s.table);   // the tile path's first barrier comes before its first lookup
+        const unsigned long long m = w.item_map[g];
+        const unsigned int di = (unsigned int)m;
+        const unsigned long long tile = m >> 32;
+        const BatchDoc b = docs[di];
+        const unsigned int epoch = w.hdr->epoch;
+        if (g < n8)
+            batch_item<U8Dir, U>(s.w.u8, s.table, b, di, tile, g, epoch, src_base, dst_base, results, w);
+        else
+            batch_item<U16Dir, U>(s.w.u16, s.table, b, di, tile, g, epoch, src_base, dst_base, results, w);
         return;
-    const unsigned long long m = w.item_map[i];
-    const unsigned int di = (unsigned int)m;
-    const unsigned long long tile = m >> 32;
+    }
+    const unsigned long long j0 = (g - nt) * kWaves;   // this workgroup's first small document
+    if (j0 >= smalls)
+        return;
+    build_pair_table(s.table);
+    __syncthreads();
+    const unsigned int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned long long j = j0 + wave;
+    if (j >= smalls)
+        return;
+    const unsigned int di = (unsigned int)w.item_map[nt + j];
     const BatchDoc b = docs[di];
-    const unsigned int epoch = w.hdr->epoch;
-    if (i < n8)
-        batch_item<U8Dir, U>(s.u8, b, di, tile, i, epoch, src_base, dst_base, results, w);
-    else
-        batch_item<U16Dir, U>(s.u16, b, di, tile, i, epoch, src_base, dst_base, results, w);
+    batch_small(s.w.small[wave], s.table, b, di, src_base, dst_base, results);
 }
 
 }  // namespace hu

@@ -88,7 +88,9 @@ constexpr int kLookLanes = 32;
 // line, and the look-back's reads of one round go to distinct lines.
 constexpr unsigned int kStatusStride = 16;
 
-__device__ unsigned long long lookback(unsigned long long *status, unsigned int stride, long long first,
+// Inlined into every caller: as a call, the UTF-16 conversion kernel kept
+// 32 bytes per lane of its tile state in scratch memory around it.
+__device__ __forceinline__ unsigned long long lookback(unsigned long long *status, unsigned int stride, long long first,
                                        long long tile, unsigned int epoch, unsigned int *hang_flag)
 {
     const int lane = threadIdx.x & 63;

@@ -77,15 +77,25 @@ __device__ __forceinline__ void build_pair_table(unsigned char *table)
 // Issue all loads of tile `tile`: U chunks per thread, plus (thread 0) the
 // granules just before and just after the tile. Unmasked: settle_tile zeroes
 // what lies outside the document.
-template <int U>
+// INSIDE_FAST: tiles wholly inside the input load without guards (fewer
+// registers; the batch kernel takes it) rather than through the guarded path
+// whatever the tile (the single-buffer convert kernels measured 2-3 % faster
+// that way).
+template <int U, bool INSIDE_FAST = false>
 __device__ __forceinline__ void load_tile(const Doc &d, unsigned long long tile, uint4 q[U], uint4 &pre, uint4 &post)
 {
     const unsigned long long tv = tile * (unsigned long long)(U * kSub);
-    // guarded loads whatever the tile (an unguarded branch for tiles wholly
-    // inside the input measured 2-3 % slower here)
+    if (INSIDE_FAST && tv >= d.off_b && tv + (unsigned long long)U * kSub <= d.end_b) {
+        const uint4 *g = reinterpret_cast<const uint4 *>(d.base + tv) + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-        q[u] = load_granule_raw(d.base, tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b, d.end_b);
+        for (int u = 0; u < U; ++u)
+            q[u] = g[u * kBlock];
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = load_granule_raw(d.base, tv + (unsigned long long)u * kSub + threadIdx.x * kChunk, d.off_b,
+                                    d.end_b);
+    }
     if (threadIdx.x == 0) {
         pre = load_granule_raw(d.base, tv >= 16 ? tv - 16 : 0, d.off_b, d.end_b);
         post = load_granule_raw(d.base, tv + (unsigned long long)U * kSub, d.off_b, d.end_b);
@@ -351,15 +361,18 @@ __device__ __forceinline__ void block_scan_multi(const unsigned int c[U], unsign
 // global units [gbase + shift, gbase + shift + w), where unit gbase sits at a
 // 16-byte aligned address; nothing at or past `cap` is written. SWAP: 16-bit
 // units leave big endian.
-template <class Dir, bool SWAP = false>
+// NT threads take part (t: this thread's index among them); STAGE: the
+// staging buffer's capacity in units.
+template <class Dir, bool SWAP = false, unsigned int NT = kBlock, unsigned int STAGE = Dir::kStageUnits>
 __device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned int shift, unsigned int w,
-                                         typename Dir::Out *dst, long long gbase, unsigned long long cap)
+                                         typename Dir::Out *dst, long long gbase, unsigned long long cap,
+                                         unsigned int t = threadIdx.x)
 {
     using Out = typename Dir::Out;
     constexpr unsigned int G = 16 / sizeof(Out);
     unsigned int span = shift + w;
-    if (span > Dir::kStageUnits)
-        span = Dir::kStageUnits;   // only on invalid input
+    if (span > STAGE)
+        span = STAGE;   // only on invalid input
     const unsigned int groups = (span + G - 1) / G;
     // The usual case: all of [gbase + shift, gbase + span) inside [0, cap).
     // Whole groups are then copied with no tests, and threads 0..2G-1 store
@@ -367,14 +380,14 @@ __device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned 
     const bool fits = gbase + (long long)shift >= 0 && (unsigned long long)(gbase + (long long)span) <= cap;
     if (fits) {
         const unsigned int gb = (shift + G - 1) / G, ge = span / G;   // whole groups: [gb, ge)
-        for (unsigned int g = gb + threadIdx.x; g < ge; g += kBlock) {
+        for (unsigned int g = gb + t; g < ge; g += NT) {
             const unsigned int i0 = g * G;
             const uint4 v = *reinterpret_cast<const uint4 *>(out + i0);
             *reinterpret_cast<uint4 *>(dst + (gbase + (long long)i0)) = SWAP ? swap16(v) : v;
         }
         const unsigned int head_end = gb * G < span ? gb * G : span;
         const unsigned int tail_begin = ge > gb ? ge * G : head_end;
-        const unsigned int t = threadIdx.x;
+        static_assert(2 * G <= NT, "threads for both partial groups");
         const unsigned int i = t < G ? shift + t : tail_begin + (t - G);
         if (t < 2 * G && (t < G ? i < head_end : i < span)) {
             const Out v = out[i];
@@ -382,7 +395,7 @@ __device__ __forceinline__ void copy_out(const typename Dir::Out *out, unsigned 
         }
         return;
     }
-    for (unsigned int g = threadIdx.x; g < groups; g += kBlock) {
+    for (unsigned int g = t; g < groups; g += NT) {
         const unsigned int i0 = g * G;
         const long long j0 = gbase + (long long)i0;
         if (i0 >= shift && i0 + G <= span && j0 >= 0 && (unsigned long long)j0 + G <= cap) {
@@ -654,18 +667,20 @@ struct Chain {
 // One tile of a document in a look-back chain: load, validate, count, scan,
 // publish, look back; thread 0 of the document's last tile then calls
 // fin(total output units); in convert mode the tile's output is written.
-// The pair table must already be in s.table. All threads must call.
+// The pair table must already be in `table` (LDS). All threads must call.
 // SWAP_IN: big-endian UTF-16 input; SWAP_OUT: big-endian UTF-16 output.
-template <class Dir, int U, int MODE, bool SWAP_IN = false, bool SWAP_OUT = false, class Finisher>
-__device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc &d, unsigned long long tile,
-                                             unsigned long long n_tiles, const Chain &cx, Finisher fin)
+template <class Dir, int U, int MODE, bool SWAP_IN = false, bool SWAP_OUT = false, bool INSIDE_FAST = false,
+          class Shared, class Finisher>
+__device__ __forceinline__ void chained_tile(Shared &s, const unsigned char *table, const Doc &d,
+                                             unsigned long long tile, unsigned long long n_tiles, const Chain &cx,
+                                             Finisher fin)
 {
     using Out = typename Dir::Out;
     const int tid = threadIdx.x;
     TileRegs<U> t;
     t.e = &s.edges;
     uint4 pre = make_uint4(0, 0, 0, 0), post = make_uint4(0, 0, 0, 0);
-    load_tile<U>(d, tile, t.q, pre, post);
+    load_tile<U, INSIDE_FAST>(d, tile, t.q, pre, post);
     settle_tile<U, SWAP_IN>(s.edges, d, tile, t, pre, post);
     __syncthreads();
 
@@ -675,7 +690,7 @@ __device__ __forceinline__ void chained_tile(ConvertShared<Dir, U> &s, const Doc
     if (MODE == kTrusted)
         count_tile<Dir, U>(t, d, tile, c);
     else
-        analyze_tile<Dir, U, MODE != kValidate>(t, s.table, d, tile, c, my_flag, cls);
+        analyze_tile<Dir, U, MODE != kValidate>(t, table, d, tile, c, my_flag, cls);
     unsigned long long tile_flag = ~0ull;
     unsigned int excl[U], tot[U];
     block_scan_multi<U, MODE != kTrusted>(c, excl, tot, s.scan, my_flag, s.red, &tile_flag);
@@ -762,7 +777,7 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
     const Chain cx{status, 0ull, tile, epoch, &hdr->err_key, &hdr->hang, kStatusStride};
     unsigned long long *s_wrap = &s.red[0];
     unsigned long long wrap_total = 0;   // thread 0 of the last tile, in the wrapping call
-    chained_tile<Dir, U, MODE, SWAP_IN, SWAP_OUT>(s, d, tile, n_tiles, cx, [&](unsigned long long total) {
+    chained_tile<Dir, U, MODE, SWAP_IN, SWAP_OUT>(s, s.table, d, tile, n_tiles, cx, [&](unsigned long long total) {
         if (wraps)
             wrap_total = total;
         else

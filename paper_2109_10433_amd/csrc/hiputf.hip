@@ -168,7 +168,7 @@ BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
 {
     BatchLayout l;
     // the smallest tile is one 4 KiB sub-tile; each document adds at most two
-    // partial tiles (alignment offset and tail)
+    // partial tiles (alignment offset and tail), a small document one item
     l.item_cap = total_input_bytes / kSub + 2ull * n_docs + 1;
     l.status = kHeaderBytes;
     l.first = align256(l.status + 8ull * l.item_cap);
@@ -176,14 +176,18 @@ BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
     l.map = align256(l.err + 8ull * n_docs);
     l.block = align256(l.map + 8ull * l.item_cap);
     l.n_blocks = (unsigned int)((n_docs + kPlanBlock - 1ull) / kPlanBlock);
-    l.total = align256(l.block + 16ull * l.n_blocks);
+    l.total = align256(l.block + 8ull * kCounts * l.n_blocks);
     return l;
 }
+
+// Sub-tiles per tile item that the batch kernel is built for.
+bool batch_sub_tiles_ok(unsigned int U) { return U == 1 || U == 2 || U == 4 || U == 6; }
 
 const void *batch_run_kernel(unsigned int U)
 {
 #define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
-    return U == 1 ? HU_K(k_batch_run<1>) : U == 2 ? HU_K(k_batch_run<2>) : HU_K(k_batch_run<4>);
+    return U == 1 ? HU_K(k_batch_run<1>) : U == 2 ? HU_K(k_batch_run<2>) : U == 4 ? HU_K(k_batch_run<4>)
+                                                                                 : HU_K(k_batch_run<6>);
 #undef HU_K
 }
 
@@ -220,7 +224,7 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     if (ws_bytes < l.total || l.item_cap >= 0x7FFFFFFFull)
         return HU_ERR_INVALID_ARGUMENT;
     const unsigned int U = (tuning && tuning->sub_tiles) ? tuning->sub_tiles : kBatchDefaultU;
-    if (U != 1 && U != 2 && U != 4)
+    if (!batch_sub_tiles_ok(U))
         return HU_ERR_INVALID_ARGUMENT;
     char *base = reinterpret_cast<char *>(ws);
     BatchWs w{reinterpret_cast<BatchHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
@@ -250,15 +254,17 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     fill_grid = fill_grid < 2048 ? fill_grid : 2048;
     hipLaunchKernelGGL(k_batch_fill, dim3((unsigned int)fill_grid), dim3(256), 0, stream, bd, n_docs, src, w,
                        tile_bytes);
-    // upper bound on the items at this tile size (the plan may need fewer:
-    // the surplus workgroups leave at once); a launch holds at most 2^32 - 1
-    // work-items, so larger bounds take several launches in item order
+    // Workgroups for upper bounds on the tile items at this tile size and on
+    // the small documents (the plan may need fewer: surplus workgroups leave
+    // at once). A launch holds at most 2^32 - 1 work-items, so more
+    // workgroups take several launches in order.
     const unsigned long long items = total_input_bytes / tile_bytes + 2ull * n_docs + 1;
+    const unsigned long long groups = items + ((unsigned long long)n_docs + kWaves - 1) / kWaves;
     constexpr unsigned long long kMaxGrid = 0xFFFFFFFFull / kBlock;
     const void *fn = batch_run_kernel(U);
     const size_t pad = lds_pad(fn, tuning ? tuning->groups_per_cu : 0);
-    for (unsigned long long base = 0; base < items; base += kMaxGrid) {
-        const unsigned long long grid = items - base < kMaxGrid ? items - base : kMaxGrid;
+    for (unsigned long long base = 0; base < groups; base += kMaxGrid) {
+        const unsigned long long grid = groups - base < kMaxGrid ? groups - base : kMaxGrid;
         void *args[] = {&bd, &src, &dst, &results, &w, &base};
         if (hipLaunchKernel(fn, dim3((unsigned int)grid), dim3(kBlock), args, pad, stream) != hipSuccess)
             return HU_ERR_DEVICE;
@@ -718,7 +724,7 @@ int hu_tune_batch(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return HU_ERR_DEVICE;
-    const unsigned int subs[] = {1, 2, 4};
+    const unsigned int subs[] = {1, 2, 4, 6};
     const unsigned int gpcs[] = {2, 4, 6, 0};
     const int reps = 3;
     double best_t = 1e300;
@@ -793,7 +799,7 @@ int hu_tuning_lookup(const char *key, hu_tuning *out)
         }
     }
     std::fclose(f);
-    if (!found || (t.sub_tiles != 1 && t.sub_tiles != 2 && t.sub_tiles != 4))
+    if (!found || !hu::batch_sub_tiles_ok(t.sub_tiles))
         return HU_ERR_INVALID_ARGUMENT;
     *out = t;
     return HU_OK;

@@ -38,6 +38,8 @@ struct U16Dir {
     // staging bound per 4 KiB sub-tile (2048 words): valid input gives at most
     // three bytes per word plus one (a high surrogate in the last word)
     static constexpr unsigned int kStageUnits = 3 * (kSub / 2) + 48;
+    // the same bound for one 1 KiB piece (a wave's share of a small document)
+    static constexpr unsigned int kPieceStageUnits = 3 * (64 * kChunk / 2) + 48;
 
     // word i (-2..9) of x[0..5]
     __device__ __forceinline__ static unsigned int word(const unsigned int x[6], int i)

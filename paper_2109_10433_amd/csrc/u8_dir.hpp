@@ -120,6 +120,8 @@ struct U8Dir {
     // staging bound per 4 KiB sub-tile: valid input gives at most one word per
     // byte plus one (a four-byte lead in the last byte)
     static constexpr unsigned int kStageUnits = kSub + 40;
+    // the same bound for one 1 KiB piece (a wave's share of a small document)
+    static constexpr unsigned int kPieceStageUnits = 64 * kChunk + 40;
 
     // UTF-16 words of the characters that start in the chunk, without any
     // validation (words per lead as in the paper's non-validating transcoder:

@@ -129,7 +129,7 @@ def test_batch_mixed_ops(texts):
     run_and_check(items, rng, label="mixed")
 
 
-@pytest.mark.parametrize("sub_tiles,groups", [(1, 1), (2, 2), (4, 0), (1, 0), (4, 6)])
+@pytest.mark.parametrize("sub_tiles,groups", [(1, 1), (2, 2), (4, 0), (1, 0), (4, 6), (6, 0), (6, 3)])
 def test_batch_tunings_agree(texts, sub_tiles, groups):
     rng = np.random.default_rng(7 + sub_tiles * 10 + groups)
     sizes = [0, 1, 7, 64, 4096, 5000, 9000, 40000]
@@ -294,7 +294,7 @@ def test_batch_tuner_and_cache(texts, tmp_path, monkeypatch):
     b = hu.Batch(docs, torch.from_numpy(src).cuda(), torch.zeros(dst_size, dtype=torch.uint8, device="cuda"))
     say("tuner")
     best, us = b.tune("test-mix")
-    assert best.sub_tiles in (1, 2, 4) and best.groups_per_cu in (0, 2, 4, 6) and us > 0
+    assert best.sub_tiles in (1, 2, 4, 6) and best.groups_per_cu in (0, 2, 4, 6) and us > 0
     got = hu.tuning_lookup("test-mix")
     assert got is not None and (got.sub_tiles, got.groups_per_cu) == (best.sub_tiles, best.groups_per_cu)
     assert hu.tuning_lookup("no-such-key") is None

@@ -441,8 +441,8 @@ __device__ __forceinline__ void workgroup_exit(unsigned long long my_total, unsi
 // ------------------------------------------------------------ validate / length
 // A wave-tile is P pieces of 1 KiB, a piece one 16-byte load per lane; wave w
 // of a grid of W waves takes wave-tiles w, w + W, w + 2W, ..., issues all
-// loads of one at once and analyses each piece as soon as its load is in
-// (the other waves of the SIMD keep memory busy meanwhile). A lane's
+// loads of the next one before it analyses the current one, each piece as
+// soon as its load is in. A lane's
 // neighbouring dwords come from the adjacent lanes by DPP rotations:
 // lane 0's dword before from lane 63 of the piece before (of the same
 // register), lane 63's dword after from lane 0 of the piece after, and at the
@@ -610,10 +610,21 @@ __global__ __launch_bounds__(kBlock) void k_scan(Doc d, unsigned long long n_til
     // index and everything derived from it stay in scalar registers
     const unsigned int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     unsigned long long wt = (unsigned long long)blockIdx.x * kWaves + wave;
-    for (; wt < n_tiles; wt += stride) {
+    // the loads of the next wave-tile are issued before this one is
+    // analysed (the last round reloads its own wave-tile, never used)
+    if (wt < n_tiles) {
         WaveTile<P> t;
         load_wave_tile<P>(d, wt, t);
-        scan_wave_tile<Dir, P, MODE == kLength, SWAP>(t, s.table, d, wt, my_total, my_flag);
+        for (;;) {
+            const unsigned long long wn = wt + stride;
+            WaveTile<P> nx;
+            load_wave_tile<P>(d, wn < n_tiles ? wn : wt, nx);
+            scan_wave_tile<Dir, P, MODE == kLength, SWAP>(t, s.table, d, wt, my_total, my_flag);
+            if (wn >= n_tiles)
+                break;
+            t = nx;
+            wt = wn;
+        }
     }
     const CallInfo c{d.base + d.off_b, d.n, d.cap, MODE == kLength ? Dir::kOpLength : Dir::kOpValidate};
     workgroup_exit(my_total, my_flag, s.red, c, hdr, status, status_cap, out, &s.flag, MODE == kLength);

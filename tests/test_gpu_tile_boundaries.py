@@ -36,8 +36,8 @@ LARGE = 64 << 20             # UTF-8 inputs of this size and more take the large
 # (op, input units, tile bytes): mirrors the kernels' tile choice (convert:
 # a workgroup's tile; validate / length: a wave's tile)
 TILES = [
-    (0, 1000, 4 * PIECE), (1, 1000, 4 * PIECE), (2, 1000, 5 * SUB), (2, LARGE, 6 * SUB),
-    (3, 1000, 4 * PIECE), (4, 1000, 4 * PIECE), (5, 1000, 6 * SUB),
+    (0, 1000, 2 * PIECE), (1, 1000, 2 * PIECE), (2, 1000, 5 * SUB), (2, LARGE, 6 * SUB),
+    (3, 1000, 2 * PIECE), (4, 1000, 4 * PIECE), (5, 1000, 6 * SUB),
 ]
 U8_FN = {0: "validate", 1: "length", 2: "convert"}
 U16_FN = {3: "validate", 4: "length", 5: "convert"}

@@ -850,6 +850,9 @@ def main() -> int:
     # oracle's, which also gives the single-thread CPU figures (each leg timed
     # on its own: the same inputs, one pass).
     host = recs.cpu().numpy()
+    # input copies that some warm-up or timed step used (the others' records
+    # were never written)
+    ran = sorted({s % copies for s in range(args.warmup)} | {s % copies for s in range(args.steps)})
     cpu_legs = {op: {"bytes": 0, "chars": 0, "s": 0.0, "profiles": {}} for op in
                 ("u8u16", "u16u8", "len8", "len16", "val8", "val16")}
     oracle_checked = {"results": 0, "outputs": 0, "output_units": 0}
@@ -880,7 +883,7 @@ def main() -> int:
             leg["profiles"][p] = {"GBps": round(nb / sec / 1e9, 3), "Gchar_per_s": round(chars / sec / 1e9, 3)}
         want = {"u8u16": r8, "nv8u16": r8, "u8u16be": r8, "u16u8": r16, "nv16u8": r16, "u16beu8": r16,
                 "len8": rl8, "len16": rl16, "val8": rv8, "val16": rv16}
-        for c in range(copies):
+        for c in ran:
             for i, (op, pp, _, _) in enumerate(calls[c]):
                 if pp != p:
                     continue

@@ -71,13 +71,20 @@ KernelChoice choose_kernel(int op, unsigned long long n_bytes)
     switch (op) {
     case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kPValidate8>), kPValidate8 * kPieceBytes, false};
     case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kPLength8>), kPLength8 * kPieceBytes, false};
-    case HU_OP_CONVERT_UTF8_TO_UTF16LE:
-        if (n_bytes < kSmallConvert8Bytes)
-            return {HU_K(k_convert_u8<kUConvert8Small, kConvert>), (unsigned long long)kUConvert8Small * kSub, true};
-        return {HU_K(k_convert_u8<kUConvert8, kConvert>), (unsigned long long)kUConvert8 * kSub, true};
+    case HU_OP_CONVERT_UTF8_TO_UTF16LE: {
+        const int u = class_sub_tiles(kConvert8Classes, n_bytes);
+        const void *fn = u == 1 ? HU_K(k_convert_u8<1, kConvert>) : u == 2 ? HU_K(k_convert_u8<2, kConvert>)
+                       : u == 5 ? HU_K(k_convert_u8<5, kConvert>) : HU_K(k_convert_u8<6, kConvert>);
+        return {fn, (unsigned long long)u * kSub, true};
+    }
     case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kPValidate16>), kPValidate16 * kPieceBytes, false};
     case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kPLength16>), kPLength16 * kPieceBytes, false};
-    default: return {HU_K(k_convert_u16<kUConvert16, kConvert>), (unsigned long long)kUConvert16 * kSub, true};
+    default: {
+        const int u = class_sub_tiles(kConvert16Classes, n_bytes);
+        const void *fn = u == 1 ? HU_K(k_convert_u16<1, kConvert>) : u == 2 ? HU_K(k_convert_u16<2, kConvert>)
+                                                                          : HU_K(k_convert_u16<6, kConvert>);
+        return {fn, (unsigned long long)u * kSub, true};
+    }
     }
 #undef HU_K
 }
@@ -398,15 +405,9 @@ hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, uns
 // device, looked up once per device.
 constexpr unsigned long long kNoAllocMaxBytes = HU_NOALLOC_MAX_BYTES;
 constexpr size_t kScratchBytes = 1536u << 10;
-constexpr unsigned long long scratch_need(unsigned long long max_bytes, unsigned long long tile_bytes)
-{
-    // 15 bytes of source alignment offset at most
-    return kHeaderBytes + 8ull * kStatusStride * ((max_bytes + 15 + tile_bytes - 1) / tile_bytes);
-}
-static_assert(kNoAllocMaxBytes >= kSmallConvert8Bytes, "tile choice below");
-static_assert(scratch_need(kNoAllocMaxBytes, (unsigned long long)kUConvert8 * kSub) <= kScratchBytes &&
-                  scratch_need(kSmallConvert8Bytes, (unsigned long long)kUConvert8Small * kSub) <= kScratchBytes,
-              "scratch holds the status words of the largest input");
+static_assert(kHeaderBytes + 8ull * kStatusStride * class_max_tiles(kConvert8Classes, kNoAllocMaxBytes, kSub) <=
+                  kScratchBytes,
+              "scratch holds the status words of any input the entry point takes");
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -535,13 +536,15 @@ size_t hu_workspace_bytes(int op, size_t n_units)
         return 0;
     // worst case over source alignments: 15 bytes of offset
     const unsigned long long bytes = op >= HU_OP_VALIDATE_UTF16LE ? 2ull * n_units : n_units;
-    // the smallest tile the operation may take: enough for any smaller input
-    // too; validate / length keep no status words
-    const hu::KernelChoice kc = hu::choose_kernel(op, 0);
-    if (!kc.one_group_per_tile)
+    // validate / length keep no status words; a conversion needs one per tile
+    // of the most tiles any input of at most n units takes (smaller inputs
+    // take smaller tiles)
+    if (!hu::choose_kernel(op, 0).one_group_per_tile)
         return hu::kHeaderBytes;
-    const unsigned long long tb = kc.tile_bytes;
-    return hu::kHeaderBytes + 8ull * hu::kStatusStride * ((bytes + 15 + tb - 1) / tb);
+    const unsigned long long tiles = op == HU_OP_CONVERT_UTF8_TO_UTF16LE
+                                         ? hu::class_max_tiles(hu::kConvert8Classes, bytes, hu::kSub)
+                                         : hu::class_max_tiles(hu::kConvert16Classes, bytes, hu::kSub);
+    return hu::kHeaderBytes + 8ull * hu::kStatusStride * tiles;
 }
 
 size_t hu_tile_bytes(int op, size_t n_units)

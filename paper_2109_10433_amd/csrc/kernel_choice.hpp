@@ -9,18 +9,55 @@
 namespace hu {
 
 // Convert tiles: sub-tiles of 4 KiB per tile (one per workgroup); bigger
-// tiles mean fewer look-backs per byte, more registers fewer waves per SIMD.
-// Measured: UTF-8 input is fastest at 6 (68 registers, seven waves per SIMD;
-// 5 fits eight waves but leaves one- and two-byte text 5 % slower, 7 and 8
-// slow down three- and four-byte text); UTF-16 input at 6 (64 registers; 8
-// and 10 are far slower).
+// tiles mean fewer look-backs per byte, more registers fewer waves per SIMD,
+// and more serial work per workgroup. Large inputs: UTF-8 is fastest at 6
+// (68 registers, seven waves per SIMD; 5 fits eight waves but leaves one- and
+// two-byte text 5 % slower, 7 and 8 slow down three- and four-byte text),
+// UTF-16 at 6 (64 registers; 8 and 10 are far slower). Smaller inputs take
+// smaller tiles, which spread them over more of the chip and shorten each
+// workgroup's serial part. Size classes by input bytes, from the measured
+// crossovers on mixed text (1..63 MiB, tiles of 1, 2, 5 / 6 sub-tiles):
+// UTF-8 1 MiB 7.8 us at 1 sub-tile against 13.7 at 5, 16 MiB 24.9 us at 2
+// against 27.3 at 5, 5 ahead from 24 MiB on; UTF-16 1 MiB 8.9 against 23.8
+// at 6, 32 MiB 41.3 at 2 against 45.1 at 6, 6 ahead from 48 MiB on.
+struct TileClass {
+    unsigned long long below;   // inputs of fewer bytes than this (and more than the class before)
+    int sub_tiles;
+};
+constexpr TileClass kConvert8Classes[] = {
+    {4ull << 20, 1}, {24ull << 20, 2}, {64ull << 20, 5}, {~0ull, 6}};
+constexpr TileClass kConvert16Classes[] = {{8ull << 20, 1}, {48ull << 20, 2}, {~0ull, 6}};
+// the variants (no validation, big-endian UTF-16) keep the large-input size
 constexpr int kUConvert8 = 6;
-// UTF-8 -> UTF-16LE inputs below kSmallConvert8Bytes take the 5 sub-tile
-// kernel instead: there more, shorter tiles spread a small input over more of
-// the chip (1 MiB: 13 instead of 16 us).
-constexpr int kUConvert8Small = 5;
-constexpr unsigned long long kSmallConvert8Bytes = 64ull << 20;
 constexpr int kUConvert16 = 6;
+
+template <int N>
+constexpr int class_sub_tiles(const TileClass (&c)[N], unsigned long long n_bytes)
+{
+    for (int i = 0; i < N; ++i)
+        if (n_bytes < c[i].below)
+            return c[i].sub_tiles;
+    return c[N - 1].sub_tiles;
+}
+
+// Largest tile count any input of at most n_bytes takes (15 bytes of source
+// alignment offset at most): the status words a workspace for such inputs
+// must hold.
+template <int N>
+constexpr unsigned long long class_max_tiles(const TileClass (&c)[N], unsigned long long n_bytes,
+                                             unsigned long long sub_bytes)
+{
+    unsigned long long lo = 0, most = 0;
+    for (int i = 0; i < N && lo <= n_bytes; ++i) {
+        const unsigned long long top = (c[i].below - 1 < n_bytes ? c[i].below - 1 : n_bytes) + 15;
+        const unsigned long long tb = (unsigned long long)c[i].sub_tiles * sub_bytes;
+        const unsigned long long t = (top + tb - 1) / tb;
+        most = t > most ? t : most;
+        lo = c[i].below;
+    }
+    return most;
+}
+
 // Validate / length: pieces of 1 KiB (one 16-byte load per lane) per
 // wave-tile, the unit a wave works on alone; a wave analyses one wave-tile
 // while the loads of its next one are in flight. Measured (P = 1..4 pieces):

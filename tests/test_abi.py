@@ -72,12 +72,30 @@ def test_tile_bytes_on_the_host():
     header alone."""
     from paper_2109_10433_amd import binding as hu
     sub, piece = 4096, 1024
-    want = {0: 2 * piece, 1: 2 * piece, 2: 5 * sub, 3: 2 * piece, 4: 4 * piece, 5: 6 * sub}
+    want = {0: 2 * piece, 1: 2 * piece, 2: 1 * sub, 3: 2 * piece, 4: 4 * piece, 5: 1 * sub}
     for op in (0, 1, 3, 4):
         assert hu.lib.hu_workspace_bytes(op, 1 << 28) == 256
-    assert hu.lib.hu_workspace_bytes(2, 1 << 20) == 256 + 128 * ((((1 << 20) + 15) + 5 * sub - 1) // (5 * sub))
     for op, tb in want.items():
         assert hu.lib.hu_tile_bytes(op, 1000) == tb
-    assert hu.lib.hu_tile_bytes(2, (64 << 20) - 1) == 5 * sub
-    assert hu.lib.hu_tile_bytes(2, 64 << 20) == 6 * sub
+    mib = 1 << 20
+    # conversion tiles by input size: UTF-8 (units = bytes) 1, 2, 5, 6 sub-tiles
+    # below 4, 24, 64 MiB and above; UTF-16 (units = words) 1, 2, 6 below 8,
+    # 48 MiB of input and above
+    for n, u in ((4 * mib - 1, 1), (4 * mib, 2), (24 * mib - 1, 2), (24 * mib, 5), (64 * mib - 1, 5),
+                 (64 * mib, 6)):
+        assert hu.lib.hu_tile_bytes(2, n) == u * sub, n
+    for n, u in ((4 * mib - 1, 1), (4 * mib, 2), (24 * mib - 1, 2), (24 * mib, 6)):
+        assert hu.lib.hu_tile_bytes(5, n) == u * sub, n
+
+    def tiles(nbytes, tb):
+        return (nbytes + 15 + tb - 1) // tb
+
+    # a workspace for n units holds the status words of the most tiles any
+    # input of at most n units takes
+    assert hu.lib.hu_workspace_bytes(2, mib) == 256 + 128 * tiles(mib, sub)
+    n = 256 * mib
+    most = max(tiles(4 * mib - 1, sub), tiles(24 * mib - 1, 2 * sub), tiles(64 * mib - 1, 5 * sub), tiles(n, 6 * sub))
+    assert hu.lib.hu_workspace_bytes(2, n) == 256 + 128 * most
+    most16 = max(tiles(8 * mib - 1, sub), tiles(48 * mib - 1, 2 * sub), tiles(2 * n, 6 * sub))
+    assert hu.lib.hu_workspace_bytes(5, n) == 256 + 128 * most16
     assert hu.lib.hu_tile_bytes(6, 10) == 0 and hu.lib.hu_tile_bytes(-1, 10) == 0

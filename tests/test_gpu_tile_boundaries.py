@@ -8,10 +8,11 @@ two tiles, meets two independent pieces of work (section 4: blocks restart at
 character boundaries; the input's tail). The tile sizes are mirrored here and
 asserted against the library (hu_tile_bytes); every UTF-8 error kind and
 arbitrary byte values are put at -6..+6 bytes around two boundaries of every
-UTF-8 kernel, including the largest-tile conversion kernel that inputs of
-64 MiB and more take (there also around the last boundary), and the four
-surrogate values and split surrogate pairs around two boundaries of every
-UTF-16 kernel, at two source alignments. Results (kind and position) and
+UTF-8 kernel, including the conversion kernels of the larger tile classes
+that inputs of 4, 24 and 64 MiB and more take (there also around the last
+boundary), and the four surrogate values and split surrogate pairs around
+two boundaries of every UTF-16 kernel, at two source alignments, and around
+the tile boundaries of the larger UTF-16 conversion classes. Results (kind and position) and
 outputs are compared with the oracle, bit for bit.
 """
 from __future__ import annotations
@@ -32,12 +33,14 @@ if torch.cuda.is_available():
 
 SUB = 4096
 PIECE = 1024                 # validate / length: a wave's 1 KiB piece (one 16-byte load per lane)
-LARGE = 64 << 20             # UTF-8 inputs of this size and more take the largest convert tiles
+MIB = 1 << 20
+LARGE = 64 * MIB             # UTF-8 inputs of this size and more take the largest convert tiles
 # (op, input units, tile bytes): mirrors the kernels' tile choice (convert:
 # a workgroup's tile; validate / length: a wave's tile)
 TILES = [
-    (0, 1000, 2 * PIECE), (1, 1000, 2 * PIECE), (2, 1000, 5 * SUB), (2, LARGE, 6 * SUB),
-    (3, 1000, 2 * PIECE), (4, 1000, 4 * PIECE), (5, 1000, 6 * SUB),
+    (0, 1000, 2 * PIECE), (1, 1000, 2 * PIECE), (2, 1000, 1 * SUB), (2, 4 * MIB, 2 * SUB),
+    (2, 24 * MIB, 5 * SUB), (2, LARGE, 6 * SUB), (3, 1000, 2 * PIECE), (4, 1000, 4 * PIECE), (5, 1000, 1 * SUB),
+    (5, 4 * MIB, 2 * SUB), (5, 24 * MIB, 6 * SUB),
 ]
 U8_FN = {0: "validate", 1: "length", 2: "convert"}
 U16_FN = {3: "validate", 4: "length", 5: "convert"}
@@ -114,20 +117,29 @@ def test_utf8_errors_at_tile_boundaries(op):
     assert n_err > 0
 
 
-@pytest.fixture(scope="module")
-def large_text():
-    say("generating", LARGE + 70_000, "bytes of mixed text")
-    return wl.make_text("mix", LARGE + 70_000, wl.rng_for("tile-boundaries", "large"), encode16=False)
+# UTF-8 inputs (bytes) in the larger conversion tile classes: 2 sub-tiles
+# from 4 MiB, 5 from 24 MiB, 6 from 64 MiB
+U8_CLASSES = [(4 * MIB + 70_000, 2), (24 * MIB + 70_000, 5), (LARGE + 70_000, 6)]
+# UTF-16 inputs (words) in the larger classes: 2 sub-tiles from 8 MiB of
+# input, 6 from 48 MiB
+U16_CLASSES = [(4 * MIB + 35_000, 2), (24 * MIB + 35_000, 6)]
 
 
-def test_utf8_errors_at_largest_convert_tiles(large_text):
-    """The conversion kernel of inputs of 64 MiB and more: every error kind at
-    -6..+6 around its first two tile boundaries and the last one; the device
+@pytest.fixture(scope="module", params=U8_CLASSES, ids=lambda c: f"{c[0] >> 20}MiB")
+def u8_class_text(request):
+    n, u = request.param
+    say("generating", n, "bytes of mixed text")
+    return wl.make_text("mix", n, wl.rng_for("tile-boundaries", "large", n), encode16=False), u
+
+
+def test_utf8_errors_at_convert_tiles_of_large_inputs(u8_class_text):
+    """The conversion kernels of the larger tile classes: every error kind at
+    -6..+6 around the first two tile boundaries and the last one; the device
     copy of the text is patched in place for each case."""
-    t = large_text
+    t, u = u8_class_text
     n = t.u8.size
     T = tile_bytes(2, n)
-    assert T == 6 * SUB
+    assert T == u * SUB
     starts = t.char_starts_u8
     clean = t.u8
     dev = torch.from_numpy(clean.copy()).cuda()
@@ -156,6 +168,45 @@ def test_utf8_errors_at_largest_convert_tiles(large_text):
     ow, orr = oracle.convert_utf8_to_utf16le(clean)
     assert (int(r.error), int(r.count)) == tuple(orr)
     assert np.array_equal(out[:orr[1]].cpu().numpy().view(np.uint16), ow)
+
+
+@pytest.fixture(scope="module", params=U16_CLASSES, ids=lambda c: f"{c[0] >> 19}MiB")
+def u16_class_text(request):
+    n_words, u = request.param
+    say("generating", n_words, "words of mixed text")
+    t = wl.make_text("mix", 2 * n_words, wl.rng_for("tile-boundaries", "large16", n_words))
+    return t.u16, u
+
+
+def test_utf16_surrogates_at_convert_tiles_of_large_inputs(u16_class_text):
+    """The UTF-16 conversion kernels of the larger tile classes: the four
+    surrogate values at -6..+6 around the first two tile boundaries and the
+    last one, the device copy patched in place; then the clean text's whole
+    output against the oracle."""
+    w, u = u16_class_text
+    n = w.size
+    T = tile_bytes(5, n) // 2                    # words per tile
+    assert T == u * SUB // 2
+    dev = torch.from_numpy(w.view(np.int16).copy()).cuda()
+    out = torch.zeros(3 * n + 64, dtype=torch.uint8, device="cuda")
+    last = ((n - 1) // T) * T
+    for b in (T, 2 * T, last):
+        say("utf16 convert, tile", T, "words, boundary at", b, "of", n)
+        for d in range(-6, 7):
+            if not 0 <= b + d < n:
+                continue
+            for val in (0xD800, 0xDBFF, 0xDC00, 0xDFFF):
+                data = w.copy()
+                data[b + d] = val
+                dev[b + d] = int(np.array([val], np.uint16).view(np.int16)[0])
+                r = hu.lib.convert_utf16le_to_utf8(dev.data_ptr(), n, out.data_ptr(), out.numel(), hu.stream_handle())
+                dev[b + d] = int(w[b + d : b + d + 1].view(np.int16)[0])
+                er = tuple(oracle.convert_utf16le_to_utf8(data)[1])
+                assert (int(r.error), int(r.count)) == er, (b, d, hex(val), er)
+    r = hu.lib.convert_utf16le_to_utf8(dev.data_ptr(), n, out.data_ptr(), out.numel(), hu.stream_handle())
+    ob, orr = oracle.convert_utf16le_to_utf8(w)
+    assert (int(r.error), int(r.count)) == tuple(orr)
+    assert np.array_equal(out[:orr[1]].cpu().numpy(), ob)
 
 
 def _expect_u16(fn, words):

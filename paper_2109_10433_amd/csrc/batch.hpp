@@ -18,6 +18,8 @@
 //         document's last tile writes its result.
 #pragma once
 
+#include <type_traits>
+
 #include "engine.hpp"
 
 namespace hu {
@@ -387,10 +389,11 @@ __device__ __forceinline__ void batch_item(BatchTileShared<Dir, U> &s, const uns
         results[di] = result_from(call, key, hang, total);
         w.err[di] = 0;
     };
+    constexpr bool skip = std::is_same<Dir, U8Dir>::value;   // UTF-8 documents only
     switch (op_mode(b.op)) {
-    case kValidate: chained_tile<Dir, U, kValidate, false, false, true>(s, table, d, tile, n_tiles, cx, fin); break;
-    case kLength: chained_tile<Dir, U, kLength, false, false, true>(s, table, d, tile, n_tiles, cx, fin); break;
-    default: chained_tile<Dir, U, kConvert, false, false, true>(s, table, d, tile, n_tiles, cx, fin); break;
+    case kValidate: chained_tile<Dir, U, kValidate, false, false, true, skip>(s, table, d, tile, n_tiles, cx, fin); break;
+    case kLength: chained_tile<Dir, U, kLength, false, false, true, skip>(s, table, d, tile, n_tiles, cx, fin); break;
+    default: chained_tile<Dir, U, kConvert, false, false, true, skip>(s, table, d, tile, n_tiles, cx, fin); break;
     }
 }
 

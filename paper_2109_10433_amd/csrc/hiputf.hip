@@ -321,8 +321,8 @@ struct StreamSlot {
     std::mutex mu;
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    hu_result *d_result = nullptr;
-    hu_result *h_result = nullptr;   // pinned
+    hu_result *h_result = nullptr;   // pinned host memory the kernel writes the result to
+    hu_result *h_result_dev = nullptr;   // its device address
 };
 
 std::mutex g_slots_mu;
@@ -364,12 +364,17 @@ hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, uns
         return make_result(HU_ERR_DEVICE, 0);
     std::lock_guard<std::mutex> lk(slot->mu);
     const size_t need = workspace_need(op, src, n);
-    if (slot->d_result == nullptr) {
-        if (hipMalloc((void **)&slot->d_result, 256) != hipSuccess ||
-            hipHostMalloc((void **)&slot->h_result, sizeof(hu_result), hipHostMallocDefault) != hipSuccess) {
-            slot->d_result = nullptr;
+    if (slot->h_result == nullptr) {
+        // the result goes straight to pinned host memory: no device-to-host
+        // copy after the kernel
+        hu_result *h = nullptr;
+        if (hipHostMalloc((void **)&h, sizeof(hu_result), hipHostMallocDefault) != hipSuccess)
+            return make_result(HU_ERR_DEVICE, 0);
+        if (hipHostGetDevicePointer((void **)&slot->h_result_dev, h, 0) != hipSuccess) {
+            (void)hipHostFree(h);
             return make_result(HU_ERR_DEVICE, 0);
         }
+        slot->h_result = h;
     }
     if (slot->ws_bytes < need) {
         // the old workspace may still be in use by work queued on this stream
@@ -387,14 +392,13 @@ hu_result run_sync(int op, const void *src, unsigned long long n, void *dst, uns
         }
         slot->ws_bytes = bytes;
     }
-    const int rc = enqueue(op, src, n, dst, cap, slot->d_result, slot->ws, slot->ws_bytes, stream);
+    const int rc = enqueue(op, src, n, dst, cap, slot->h_result_dev, slot->ws, slot->ws_bytes, stream);
     if (rc != HU_OK)
         return make_result(rc, 0);
-    if (hipMemcpyAsync(slot->h_result, slot->d_result, sizeof(hu_result), hipMemcpyDeviceToHost, stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
+    if (hipStreamSynchronize(stream) != hipSuccess)
         return make_result(HU_ERR_DEVICE, 0);
-    return *slot->h_result;
+    const volatile hu_result *r = slot->h_result;
+    return make_result(r->error, r->count);
 }
 
 // ------------------------------------------------------------ static scratch
@@ -838,13 +842,12 @@ void hu_shutdown(void)
         if (hipSetDevice(kv.first.first) == hipSuccess) {
             (void)hipDeviceSynchronize();
             if (s->ws) (void)hipFree(s->ws);
-            if (s->d_result) (void)hipFree(s->d_result);
             if (s->h_result) (void)hipHostFree(s->h_result);
         }
         (void)hipSetDevice(prev);
         s->ws = nullptr;
-        s->d_result = nullptr;
         s->h_result = nullptr;
+        s->h_result_dev = nullptr;
         s->ws_bytes = 0;
     }
 }

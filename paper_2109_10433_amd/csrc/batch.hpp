@@ -8,7 +8,7 @@
 //         items of U sub-tiles of 4 KiB). Items are numbered UTF-8 tiles
 //         first, then UTF-16 tiles, then small documents, each in document
 //         order. The plan also advances the workspace epoch.
-//   fill: item -> (document, tile of the document) map.
+//   fill: one record per item: the document, its index, the tile.
 //   run:  one fused kernel for both input encodings: one workgroup per tile
 //         item, in item order, then one wave per small document. A tile
 //         waits (look-back) only for earlier tiles of its own document; a
@@ -31,8 +31,8 @@ struct BatchDoc {                     // mirrors hu_doc
 static_assert(sizeof(BatchDoc) == sizeof(hu_doc), "hu_doc layout");
 
 // Workspace of a batch call:
-//   [BatchHeader (256 B) | status, item_cap words | first_item | err | item_map
-//    | three words per block of documents (planning)]
+//   [BatchHeader (256 B) | status, item_cap words | first_item | err | items
+//    (48 B each) | three words per block of documents (planning)]
 // The status array starts at a fixed offset; everything after it moves with
 // the call's shape (document count, item capacity). Status words must never
 // hold anything but status words or zeros, so memory that earlier calls used
@@ -50,11 +50,21 @@ struct BatchHeader {
 };
 static_assert(sizeof(BatchHeader) <= kHeaderBytes, "batch header size");
 
+// Work item record, written by the fill kernel: the document's table entry
+// beside its index and the tile's, so that a run workgroup reads one record
+// (scalar loads) instead of an index and then the document table.
+struct BatchItem {
+    BatchDoc doc;
+    unsigned int di;                  // document index
+    unsigned int tile;                // tile of the document (0 for a small document)
+};
+static_assert(sizeof(BatchItem) == 48, "item record");
+
 struct BatchWs {
     BatchHeader *hdr;
     unsigned int *first_item;         // per document
     unsigned long long *err;          // per document error key
-    unsigned long long *item_map;     // per item: document index | tile index << 32
+    BatchItem *items;                 // per item
     unsigned long long *status;       // per tile item look-back status
     unsigned long long *block;        // per block of documents: UTF-8, UTF-16, small items (then their offsets)
     unsigned long long item_cap;
@@ -335,8 +345,8 @@ __global__ __launch_bounds__(kPlanBlock) void k_batch_plan1(const BatchDoc *docs
     plan_bookkeeping(w, t, &s_wrap);
 }
 
-// item -> (document, tile) map; every error key back to zero; status words
-// the plan marked for clearing.
+// The item records; every error key back to zero; status words the plan
+// marked for clearing.
 __global__ void k_batch_fill(const BatchDoc *docs, unsigned int n_docs, const uint8_t *src_base, BatchWs w,
                              unsigned long long tile_bytes)
 {
@@ -351,12 +361,9 @@ __global__ void k_batch_fill(const BatchDoc *docs, unsigned int n_docs, const ui
             continue;
         const BatchDoc b = docs[d];
         const unsigned long long t = doc_tiles(b, src_base, tile_bytes);
-        if (t == 0) {
-            w.item_map[first] = (unsigned long long)d;   // a small document: one item
-            continue;
-        }
-        for (unsigned long long k = 0; k < t; ++k)
-            w.item_map[first + k] = (unsigned long long)d | (k << 32);
+        const unsigned long long items = t ? t : 1;   // a small document: one item
+        for (unsigned long long k = 0; k < items; ++k)
+            w.items[first + k] = BatchItem{b, d, (unsigned int)k};
     }
 }
 
@@ -552,23 +559,20 @@ struct BatchShared {
 // launch to cap the workgroups resident per CU.
 template <int U>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
-void k_batch_run(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_base, hu_result *results, BatchWs w,
-                 unsigned long long base)
+void k_batch_run(const uint8_t *src_base, uint8_t *dst_base, hu_result *results, BatchWs w, unsigned long long base)
 {
     __shared__ BatchShared<U> s;
     const unsigned long long g = base + blockIdx.x;
     const unsigned long long n8 = w.hdr->items8, nt = n8 + w.hdr->items16, smalls = w.hdr->smalls;
     if (g < nt) {
         build_pair_table(s.table);   // the tile path's first barrier comes before its first lookup
-        const unsigned long long m = w.item_map[g];
-        const unsigned int di = (unsigned int)m;
-        const unsigned long long tile = m >> 32;
-        const BatchDoc b = docs[di];
+        const BatchItem it = w.items[g];
         const unsigned int epoch = w.hdr->epoch;
         if (g < n8)
-            batch_item<U8Dir, U>(s.w.u8, s.table, b, di, tile, g, epoch, src_base, dst_base, results, w);
+            batch_item<U8Dir, U>(s.w.u8, s.table, it.doc, it.di, it.tile, g, epoch, src_base, dst_base, results, w);
         else
-            batch_item<U16Dir, U>(s.w.u16, s.table, b, di, tile, g, epoch, src_base, dst_base, results, w);
+            batch_item<U16Dir, U>(s.w.u16, s.table, it.doc, it.di, it.tile, g, epoch, src_base, dst_base, results,
+                                  w);
         return;
     }
     const unsigned long long j0 = (g - nt) * kWaves;   // this workgroup's first small document
@@ -580,9 +584,8 @@ void k_batch_run(const BatchDoc *docs, const uint8_t *src_base, uint8_t *dst_bas
     const unsigned long long j = j0 + wave;
     if (j >= smalls)
         return;
-    const unsigned int di = (unsigned int)w.item_map[nt + j];
-    const BatchDoc b = docs[di];
-    batch_small(s.w.small[wave], s.table, b, di, src_base, dst_base, results);
+    const BatchItem it = w.items[nt + j];
+    batch_small(s.w.small[wave], s.table, it.doc, it.di, src_base, dst_base, results);
 }
 
 }  // namespace hu

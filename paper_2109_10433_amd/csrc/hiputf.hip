@@ -181,7 +181,7 @@ BatchLayout batch_layout(uint32_t n_docs, uint64_t total_input_bytes)
     l.first = align256(l.status + 8ull * l.item_cap);
     l.err = align256(l.first + 4ull * n_docs);
     l.map = align256(l.err + 8ull * n_docs);
-    l.block = align256(l.map + 8ull * l.item_cap);
+    l.block = align256(l.map + sizeof(BatchItem) * l.item_cap);
     l.n_blocks = (unsigned int)((n_docs + kPlanBlock - 1ull) / kPlanBlock);
     l.total = align256(l.block + 8ull * kCounts * l.n_blocks);
     return l;
@@ -236,7 +236,7 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     char *base = reinterpret_cast<char *>(ws);
     BatchWs w{reinterpret_cast<BatchHeader *>(base), reinterpret_cast<unsigned int *>(base + l.first),
               reinterpret_cast<unsigned long long *>(base + l.err),
-              reinterpret_cast<unsigned long long *>(base + l.map),
+              reinterpret_cast<BatchItem *>(base + l.map),
               reinterpret_cast<unsigned long long *>(base + l.status),
               reinterpret_cast<unsigned long long *>(base + l.block), l.item_cap};
     const BatchDoc *bd = reinterpret_cast<const BatchDoc *>(docs);
@@ -272,7 +272,7 @@ int batch_enqueue(const hu_doc *docs, uint32_t n_docs, uint64_t total_input_byte
     const size_t pad = lds_pad(fn, tuning ? tuning->groups_per_cu : 0);
     for (unsigned long long base = 0; base < groups; base += kMaxGrid) {
         const unsigned long long grid = groups - base < kMaxGrid ? groups - base : kMaxGrid;
-        void *args[] = {&bd, &src, &dst, &results, &w, &base};
+        void *args[] = {&src, &dst, &results, &w, &base};
         if (hipLaunchKernel(fn, dim3((unsigned int)grid), dim3(kBlock), args, pad, stream) != hipSuccess)
             return HU_ERR_DEVICE;
     }

@@ -75,9 +75,10 @@ enum {
 };
 
 /* ------------------------------------------------------------------------
- * Synchronous calls. Each enqueues its kernels on `stream`, waits for that
- * stream, and returns the result. Scratch memory (a 256-byte header, and for
- * the conversions 128 bytes per tile of 20 or 24 KiB of input;
+ * Synchronous calls. Each enqueues its kernel on `stream`, waits for that
+ * stream, and returns the result, which the kernel writes straight into a
+ * pinned host record. Scratch memory (a 256-byte header, and for the
+ * conversions 128 bytes per tile of 4 to 24 KiB of input, by input size;
  * hu_workspace_bytes gives the exact figure) comes from a per-device,
  * per-stream cache owned by the library
  * (freed by hu_shutdown). n = 0 returns {HU_OK, 0}; pointers may then be NULL.

@@ -275,7 +275,7 @@ typedef struct {
 
 /* Launch shape of the batch kernels (see hu_tune_batch). */
 typedef struct {
-    uint32_t sub_tiles;       /* 4 KiB input sub-tiles per work item: 1, 2 or 4 (0 = default) */
+    uint32_t sub_tiles;       /* 4 KiB input sub-tiles per tile work item: 1, 2, 4 or 6 (0 = default, 2) */
     uint32_t groups_per_cu;   /* at most this many run-kernel workgroups per compute unit, enforced by
                                  reserving unused LDS (0 = as many as the kernel's resources allow) */
 } hu_tuning;
@@ -308,7 +308,7 @@ int hu_graph_launch(void *graph_exec, void *stream);
 void hu_graph_destroy(void *graph_exec);
 
 /* Autotuner: times hu_batch_run on the given batch (which it runs several
- * times) for every sub_tiles in {1, 2, 4} and groups_per_cu in {2, 4, 6, 0},
+ * times) for every sub_tiles in {1, 2, 4, 6} and groups_per_cu in {2, 4, 6, 0},
  * writes the fastest to *best and its mean time in microseconds to *best_us.
  * If `key` is non-NULL and the environment variable HIPUTF_TUNE_CACHE names a
  * file, the result is appended to that file as one JSON line

@@ -454,13 +454,19 @@ __device__ __forceinline__ void small_doc(typename Dir::Out *stage, const unsign
     constexpr bool COUNT = MODE != kValidate;
     constexpr unsigned int G = 16 / sizeof(Out);
     const unsigned int lane = threadIdx.x & 63;
+    const unsigned int n_pieces = (unsigned int)((d.end_b + kPiece - 1) / kPiece);
+    // the document's pieces only (no dwords around the wave-tile: piece_chunk
+    // takes zeros there)
     WaveTile<P> t;
-    load_wave_tile<P>(d, 0, t);
+#pragma unroll
+    for (int u = 0; u < P; ++u) {
+        const unsigned long long v = (unsigned long long)u * kPiece + lane * kChunk;
+        t.q[u] = (unsigned int)u < n_pieces ? load_granule_raw(d.base, v, d.off_b, d.end_b) : make_uint4(0, 0, 0, 0);
+    }
 #pragma unroll
     for (int u = 0; u < P; ++u)
         t.q[u] = mask_granule(t.q[u], (unsigned long long)u * kPiece + lane * kChunk, d.off_b, d.end_b);
     const unsigned long long n_b = d.end_b - d.off_b;
-    const unsigned int n_pieces = (unsigned int)((d.end_b + kPiece - 1) / kPiece);
     const unsigned int dst_mis = (unsigned int)(((uintptr_t)d.dst & 15u) / sizeof(Out));
     Out *dst = reinterpret_cast<Out *>(d.dst);
     // whether the output fits the capacity is known only at the end (the

@@ -799,7 +799,7 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
     const CallInfo call{d.base + d.off_b, d.n, d.cap, Dir::kOpConvert};
     if (n_tiles == 0) {
         if (threadIdx.x == 0)
-            finish_call(call, hdr, 0ull, status, status_cap, out, &s.red[0]);
+            finish_call(call, hdr, 0ull, out, &s.red[0]);
         __syncthreads();
         wrap_clear(status, status_cap, &s.red[0]);
         return;
@@ -815,7 +815,7 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
         if (wraps)
             wrap_total = total;
         else
-            finish_call(call, hdr, total, status, status_cap, out, s_wrap);
+            finish_call(call, hdr, total, out, s_wrap);
     });
     if (!wraps)
         return;
@@ -839,7 +839,7 @@ __device__ __forceinline__ void convert_body(Doc d, unsigned long long n_tiles, 
             }
             __builtin_amdgcn_s_sleep(4);
         }
-        finish_call(call, hdr, wrap_total, status, status_cap, out, s_wrap);
+        finish_call(call, hdr, wrap_total, out, s_wrap);
     }
     wrap_clear(status, status_cap, s_wrap);
 }

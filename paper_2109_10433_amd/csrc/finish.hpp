@@ -131,8 +131,7 @@ __device__ inline void report_flag(unsigned long long *err_key, unsigned long lo
 
 // Thread 0 of the finishing workgroup: write the result, reset the header for
 // the next call (the epoch advances). Sets *s_wrap when the epoch wrapped.
-__device__ inline void finish_call(const CallInfo &c, WsHeader *hdr, unsigned long long total,
-                                   unsigned long long *status, unsigned long long status_cap, hu_result *out,
+__device__ inline void finish_call(const CallInfo &c, WsHeader *hdr, unsigned long long total, hu_result *out,
                                    unsigned long long *s_wrap)
 {
     *out = call_result(c, hdr, total);
@@ -183,7 +182,7 @@ __device__ inline void finish_launch(const CallInfo &c, WsHeader *hdr, unsigned 
         return;
     if (threadIdx.x == 0) {
         const unsigned long long total = __hip_atomic_load(&hdr->total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        finish_call(c, hdr, total, status, status_cap, out, s_wrap);
+        finish_call(c, hdr, total, out, s_wrap);
     }
     wrap_clear(status, status_cap, s_wrap);
 }

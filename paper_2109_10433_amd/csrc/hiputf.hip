@@ -65,7 +65,7 @@ KernelChoice choose_kernel(int op, unsigned long long n_bytes)
 #define HU_K(...) reinterpret_cast<const void *>(&__VA_ARGS__)
     if ((op & kOpFlags) != 0) {   // no kernel for the combination: fn stays null
         KernelChoice kc{nullptr, (unsigned long long)kSub, true};
-        choose_variant(op, kc);
+        choose_variant(op, n_bytes, kc);
         return kc;
     }
     switch (op) {

@@ -27,9 +27,6 @@ struct TileClass {
 constexpr TileClass kConvert8Classes[] = {
     {4ull << 20, 1}, {24ull << 20, 2}, {64ull << 20, 5}, {~0ull, 6}};
 constexpr TileClass kConvert16Classes[] = {{8ull << 20, 1}, {48ull << 20, 2}, {~0ull, 6}};
-// the variants (no validation, big-endian UTF-16) keep the large-input size
-constexpr int kUConvert8 = 6;
-constexpr int kUConvert16 = 6;
 
 template <int N>
 constexpr int class_sub_tiles(const TileClass (&c)[N], unsigned long long n_bytes)
@@ -95,6 +92,6 @@ struct KernelChoice {
 };
 
 // An op with flags (variants.hip): false when the combination has no kernel.
-bool choose_variant(int op, KernelChoice &kc);
+bool choose_variant(int op, unsigned long long n_bytes, KernelChoice &kc);
 
 }  // namespace hu

@@ -8,9 +8,13 @@
 // / 110 / 10. Validation (section 3): a word in D800..DBFF must be followed by
 // one in DC00..DFFF and a word in DC00..DFFF must follow one in D800..DBFF.
 // The paper sends blocks with surrogates to a scalar path (vectorising them is
-// its stated future work, section 7); here each lane composes its pairs in
-// registers: the high word emits all four bytes and the low word none. The
-// first flagged word is exactly the first error.
+// its stated future work, section 7); here a pair's four bytes are split two
+// and two between its words: the high word gives the lead byte and the first
+// continuation byte (bits 20..12 of the code point, which come from the high
+// word alone), the low word the last two (bits 11..0: two bits of the high
+// word, ten of its own). Every word then stands for one to three bytes and
+// waves with surrogates encode without a branch per word. The first flagged
+// word is exactly the first error.
 #pragma once
 
 #include "device_common.hpp"
@@ -20,13 +24,6 @@ namespace hu {
 __device__ __forceinline__ bool is_high(unsigned int w) { return (w & 0xFC00u) == 0xD800u; }
 __device__ __forceinline__ bool is_low(unsigned int w) { return (w & 0xFC00u) == 0xDC00u; }
 
-// UTF-8 length of the character that starts at word w: 0 for the low half of
-// a pair (its high half emits the four bytes).
-__device__ __forceinline__ unsigned int utf8_bytes_of(unsigned int w)
-{
-    return w < 0x80u ? 1u : w < 0x800u ? 2u : is_high(w) ? 4u : is_low(w) ? 0u : 3u;
-}
-
 struct U16Dir {
     using Out = unsigned char;
     static constexpr int kInUnit = 2;
@@ -35,8 +32,8 @@ struct U16Dir {
     static constexpr int kOpValidate = HU_OP_VALIDATE_UTF16LE;
     static constexpr int kOpLength = HU_OP_UTF8_LENGTH_FROM_UTF16LE;
     static constexpr int kOpConvert = HU_OP_CONVERT_UTF16LE_TO_UTF8;
-    // staging bound per 4 KiB sub-tile (2048 words): valid input gives at most
-    // three bytes per word plus one (a high surrogate in the last word)
+    // staging bound per 4 KiB sub-tile (2048 words): at most three bytes per
+    // word, whatever the input
     static constexpr unsigned int kStageUnits = 3 * (kSub / 2) + 48;
     // the same bound for one 1 KiB piece (a wave's share of a small document)
     static constexpr unsigned int kPieceStageUnits = 3 * (64 * kChunk / 2) + 48;
@@ -48,10 +45,8 @@ struct U16Dir {
         return (x[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
     }
 
-    // UTF-8 bytes of the chunk's words, without any validation (a high
-    // surrogate four, a low one none): analyze's count, whose flag is not
-    // looked at (its surrogate-free waves take the cheap path; the others
-    // count word by word as below).
+    // UTF-8 bytes of the chunk's words, without any validation (two for
+    // each surrogate): analyze's count, whose flag is not looked at.
     __device__ __forceinline__ static unsigned int count_only(const unsigned int x[6])
     {
         int f;
@@ -67,12 +62,8 @@ struct U16Dir {
                                                            int *flag, unsigned int *cls)
     {
         *cls = kClassUnknown;   // emit finds its own path
-        // Waves without any word in D800..DFFF have nothing to flag; each
-        // word then takes 1 + (w >= 0x80) + (w >= 0x800) UTF-8 bytes. The two
-        // words of a dword are tested together as 16-bit halves: the top bit
-        // of a half of ((x & m) + m) | x, with m = 0x7F80 (0x7800), is set
-        // exactly when its word is >= 0x80 (0x800), and no sum carries into
-        // the next half.
+        // Waves without any word in D800..DFFF have nothing to flag:
+        // min((w >> 11) ^ 0x1B, 1) is 0 for a surrogate and 1 otherwise.
         const u16x2 one = {1, 1}, sur = {0x1B, 0x1B};   // w >> 11 of D800..DFFF
         u16x2 plain = {1, 1};
 #pragma unroll
@@ -82,18 +73,8 @@ struct U16Dir {
         }
         if (!__any(__builtin_bit_cast(unsigned int, plain) != 0x00010001u)) {
             *flag = kNoFlag;
-            unsigned int count = 8;
-            if (COUNT) {
-#pragma unroll
-                for (int k = 1; k <= 4; ++k) {
-                    const unsigned int g80 = ((x[k] & 0x7F807F80u) + 0x7F807F80u) | x[k];
-                    const unsigned int g800 = ((x[k] & 0x78007800u) + 0x78007800u) | x[k];
-                    count += __popc(g80 & 0x80008000u) + __popc(g800 & 0x80008000u);
-                }
-            }
-            return COUNT ? count : 0u;
+            return COUNT ? 8u + extra_bytes(x) : 0u;
         }
-        unsigned int count = 0;
         int f = kNoFlag;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -101,10 +82,32 @@ struct U16Dir {
             const bool bad = (is_high(w) && !is_low(nw)) || (is_low(w) && !is_high(pw));
             if (bad && f == kNoFlag)
                 f = j;
-            if (COUNT)
-                count += utf8_bytes_of(w);
         }
         *flag = f;
+        if (!COUNT)
+            return 0u;
+        // a surrogate takes two bytes: one less than the other words >= 0x800
+        u16x2 kept = {0, 0};   // words outside D800..DFFF
+#pragma unroll
+        for (int k = 1; k <= 4; ++k)
+            kept += __builtin_elementwise_min((__builtin_bit_cast(u16x2, x[k]) >> 11) ^ sur, one);
+        return extra_bytes(x) + kept.x + kept.y;
+    }
+
+    // UTF-8 bytes beyond the first of the chunk's words, each word counted as
+    // (w >= 0x80) + (w >= 0x800). The two words of a dword are tested together
+    // as 16-bit halves: the top bit of a half of ((x & m) + m) | x, with
+    // m = 0x7F80 (0x7800), is set exactly when its word is >= 0x80 (0x800),
+    // and no sum carries into the next half.
+    __device__ __forceinline__ static unsigned int extra_bytes(const unsigned int x[6])
+    {
+        unsigned int count = 0;
+#pragma unroll
+        for (int k = 1; k <= 4; ++k) {
+            const unsigned int g80 = ((x[k] & 0x7F807F80u) + 0x7F807F80u) | x[k];
+            const unsigned int g800 = ((x[k] & 0x78007800u) + 0x78007800u) | x[k];
+            count += __popc(g80 & 0x80008000u) + __popc(g800 & 0x80008000u);
+        }
         return count;
     }
 
@@ -133,42 +136,10 @@ struct U16Dir {
             const unsigned int v = (x[k] & 0xF800F800u) ^ 0xD800D800u;
             sur |= ((v - 0x00010001u) & ~v & 0x80008000u) != 0;
         }
-        if (!__any(sur)) {
+        if (!__any(sur))
             emit_direct<3>(x, out, o);
-            return;
-        }
-        // Surrogates in the wave: one word at a time (text dense in pairs has
-        // a high word and an empty low word per character, where a branch-free
-        // form would store four bytes for every word).
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const unsigned int w = word(x, j), nw = word(x, j + 1);
-            const unsigned int m = utf8_bytes_of(w);
-            unsigned int b0, b1 = 0, b2 = 0, b3 = 0;
-            if (m == 4) {
-                const unsigned int cp = 0x10000u + (((w & 0x3FFu) << 10) | (nw & 0x3FFu));
-                b0 = 0xF0u | (cp >> 18);
-                b1 = 0x80u | ((cp >> 12) & 0x3Fu);
-                b2 = 0x80u | ((cp >> 6) & 0x3Fu);
-                b3 = 0x80u | (cp & 0x3Fu);
-            } else if (m == 3) {
-                b0 = 0xE0u | (w >> 12);
-                b1 = 0x80u | ((w >> 6) & 0x3Fu);
-                b2 = 0x80u | (w & 0x3Fu);
-            } else if (m == 2) {
-                b0 = 0xC0u | (w >> 6);
-                b1 = 0x80u | (w & 0x3Fu);
-            } else {
-                b0 = w;
-            }
-            if (m != 0) {
-                out[o] = (Out)b0;
-                if (m > 1) out[o + 1] = (Out)b1;
-                if (m > 2) out[o + 2] = (Out)b2;
-                if (m > 3) out[o + 3] = (Out)b3;
-            }
-            o += m;
-        }
+        else
+            emit_direct<3, true>(x, out, o);
     }
 
     // Encoding of waves whose words are all below U+0800 (one or two bytes,
@@ -205,27 +176,36 @@ struct U16Dir {
 
     // Encoding without a branch per word, for waves whose words need at most
     // MAXB bytes: 2 is the paper's section 5 cases of one and two output
-    // bytes, 3 adds three-byte words (no surrogates). Bytes of a word w:
-    // b0 = w (w < 0x80), 0xC0 | w >> 6 (w < 0x800) or 0xE0 | w >> 12; the
-    // following bytes 0x80 | six bits each, most significant first. MAXB
-    // bytes are stored for every word, words in ascending order, at the
-    // word's output offset: bytes past a word's length land where the next
-    // words start, and those overwrite them. Nothing may spill past the
-    // chunk's output (the next thread's): the last MAXB - 1 words store a
-    // byte only where the chunk's remaining words still reach (words before
-    // them are followed by at least MAXB - 1 words of at least one byte).
-    // emit uses MAXB = 3; for waves below U+0800 emit_direct2 is the same
-    // encoding two words at a time.
-    template <int MAXB>
+    // bytes, 3 adds three-byte words. A word w of n bytes is shifted left by
+    // 6(3 - n) bits into v; its lead byte is P ^ (v >> 12), with P = 0x00,
+    // 0xC0, 0xE0 for n = 1, 2, 3 (no payload bit meets a prefix bit, so the
+    // exclusive or is an or), its next bytes 0x80 | (v >> 6 & 0x3F) and
+    // 0x80 | (v & 0x3F). MAXB bytes are stored for every word, words in
+    // ascending order, at the word's output offset: bytes past a word's length
+    // land where the next words start, and those overwrite them. Nothing may
+    // spill past the chunk's output (the next thread's): the last MAXB - 1
+    // words store a byte only where the chunk's remaining words still reach
+    // (words before them are followed by at least MAXB - 1 words of at least
+    // one byte). emit uses MAXB = 3; for waves below U+0800 emit_direct2 is
+    // the same encoding two words at a time.
+    // With SUR, surrogates are two-byte words (P = 0xC0) with a value of
+    // their own in place of w. A high word h stands for bits 20..12 of the
+    // code point, u >> 2 with u = (h & 0x3FF) + 0x40; with 0xC00 added, its
+    // lead byte is 0xC0 ^ (0x30 | u >> 8) = 0xF0 | u >> 8. A low word l after h
+    // stands for bits 11..0, (h & 3) << 10 | (l & 0x3FF); with 0x1000 added,
+    // its first byte is 0xC0 ^ 0x40 ^ (bits 11..6) = 0x80 | bits 11..6.
+    template <int MAXB, bool SUR = false>
     __device__ __forceinline__ static void emit_direct(const unsigned int x[6], Out *out, unsigned int o)
     {
-        static_assert(MAXB == 2 || MAXB == 3, "no surrogates");
+        static_assert(MAXB == 2 || MAXB == 3, "at most three bytes per word");
+        static_assert(!SUR || MAXB == 3, "surrogates only beside three-byte words");
         constexpr int kSafe = 9 - MAXB;
         unsigned int len[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j);
-            len[j] = 1u + (w >= 0x80u ? 1u : 0u) + (MAXB == 3 && w >= 0x800u ? 1u : 0u);
+            const bool s = SUR && (w & 0xF800u) == 0xD800u;
+            len[j] = 1u + (w >= 0x80u ? 1u : 0u) + (MAXB == 3 && w >= 0x800u && !s ? 1u : 0u);
         }
         // reach[j]: output bytes of words j..7 (only j >= kSafe matter)
         unsigned int reach[8];
@@ -236,18 +216,27 @@ struct U16Dir {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const unsigned int w = word(x, j);
-            const unsigned int n = len[j];
-            const bool three = n == 3u;
+            const unsigned int n1 = len[j] - 1u;   // 0, 1, 2
+            unsigned int v = w;
+            if (SUR) {
+                // both values computed, then selected: the compiler keeps
+                // selects of plain values as selects, not branches
+                const unsigned int t = w & 0x3FFu;
+                const unsigned int vh = (t >> 2) + 0xC10u, vl = (((word(x, j - 1) & 3u) | 4u) << 10) | t;
+                const unsigned int vs = (w & 0x400u) == 0 ? vh : vl;
+                v = (w & 0xF800u) == 0xD800u ? vs : w;
+            }
+            v <<= 12u - 6u * n1;
             unsigned int b[3];
-            b[0] = three ? (0xE0u | (w >> 12)) : n == 2u ? (0xC0u | (w >> 6)) : w;
-            b[1] = 0x80u | ((three ? (w >> 6) : w) & 0x3Fu);
-            b[2] = 0x80u | (w & 0x3Fu);
+            b[0] = __builtin_amdgcn_ubfe(0x00E0C000u, 8u * n1, 8u) ^ (v >> 12);
+            b[1] = 0x80u | ((v >> 6) & 0x3Fu);
+            b[2] = 0x80u | (v & 0x3Fu);
 #pragma unroll
             for (int i = 0; i < MAXB; ++i) {
                 if (j < kSafe || (unsigned int)i < reach[j])
                     out[o + i] = (Out)b[i];
             }
-            o += n;
+            o += len[j];
         }
     }
 };

@@ -65,17 +65,21 @@ def test_valid_input_matches_the_oracle(profile):
 
 
 def test_invalid_input_stays_inside_the_output():
-    """Counts inflated by invalid input (every byte a four-byte lead, every
-    word a high surrogate) exceed the capacities: OUTPUT_TOO_SMALL, and no
-    write outside [dst, dst + cap); random garbage: completes, guards intact."""
+    """Counts inflated by invalid input (every byte a four-byte lead, counted
+    as two words; every word a high surrogate, counted as two bytes, against
+    one byte per word) exceed the capacities: OUTPUT_TOO_SMALL, and no write
+    outside [dst, dst + cap); random garbage: completes, guards intact."""
     rng = np.random.default_rng(4)
     for n in (1, 100, 4096, 20480 + 7, 1 << 20):
         say("non-validating on invalid input, n =", n)
         r, _, out, h = nv_u8(np.full(n, 0xF8, np.uint8))
         assert r == (hu.OUTPUT_TOO_SMALL, 2 * n)
         out.check_guards(h)
-        r, _, out, h = nv_u16(np.full(n, 0xD800, np.uint16))
-        assert r == (hu.OUTPUT_TOO_SMALL, 4 * n)
+        r, _, out, h = nv_u16(np.full(n, 0xD800, np.uint16), cap_bytes=n)
+        assert r == (hu.OUTPUT_TOO_SMALL, 2 * n)
+        out.check_guards(h)
+        r, _, out, h = nv_u16(np.full(n, 0xDC00, np.uint16))
+        assert r == (0, 2 * n)
         out.check_guards(h)
         for _ in range(3):
             r, _, out, h = nv_u8(rng.integers(0, 256, n, dtype=np.uint8), int(rng.integers(0, 16)))

@@ -30,12 +30,18 @@ __global__ void k_fill_zero(unsigned int *p, unsigned long long n_words)
 struct DeviceInfo {
     int cus = 0;
     std::map<const void *, int> blocks_per_cu;
+    std::map<std::pair<const void *, unsigned int>, size_t> lds_pads;   // (kernel, groups per CU)
 };
+
+size_t lds_pad(const void *fn, unsigned int groups_per_cu);
 
 std::mutex g_info_mu;
 std::map<int, DeviceInfo> g_info;
 
-int max_resident_blocks(const void *kernel)
+// Resident workgroups of a persistent kernel over the device: per CU, what
+// its resources allow, at most cap (0: no cap). *pad: the dynamic LDS per
+// workgroup that holds residency to cap (0 without a cap).
+int max_resident_blocks(const void *kernel, unsigned int cap = 0, size_t *pad = nullptr)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
@@ -53,7 +59,16 @@ int max_resident_blocks(const void *kernel)
             nb = 1;
         it = di.blocks_per_cu.emplace(kernel, nb).first;
     }
-    return di.cus * it->second;
+    if (pad != nullptr) {
+        *pad = 0;
+        if (cap != 0) {
+            auto pt = di.lds_pads.find({kernel, cap});
+            if (pt == di.lds_pads.end())
+                pt = di.lds_pads.emplace(std::make_pair(kernel, cap), lds_pad(kernel, cap)).first;
+            *pad = pt->second;
+        }
+    }
+    return di.cus * (cap != 0 && (int)cap < it->second ? (int)cap : it->second);
 }
 
 constexpr unsigned long long kMaxUnits = 1ull << 38;   // status values hold 40 bits
@@ -78,7 +93,8 @@ KernelChoice choose_kernel(int op, unsigned long long n_bytes)
         return {fn, (unsigned long long)u * kSub, true};
     }
     case HU_OP_VALIDATE_UTF16LE: return {HU_K(k_scan<U16Dir, kValidate, kPValidate16>), kPValidate16 * kPieceBytes, false};
-    case HU_OP_UTF8_LENGTH_FROM_UTF16LE: return {HU_K(k_scan<U16Dir, kLength, kPLength16>), kPLength16 * kPieceBytes, false};
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE:
+        return {HU_K(k_scan<U16Dir, kLength, kPLength16>), kPLength16 * kPieceBytes, false, kLength16GroupsPerCu};
     default: {
         const int u = class_sub_tiles(kConvert16Classes, n_bytes);
         const void *fn = u == 1 ? HU_K(k_convert_u16<1, kConvert>) : u == 2 ? HU_K(k_convert_u16<2, kConvert>)
@@ -139,12 +155,13 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
 
     const KernelChoice kc = choose_kernel(op, n_bytes);
     unsigned long long grid_ll = 1;   // at least one workgroup: with no tiles it only writes the result
+    size_t pad = 0;                   // dynamic LDS that holds residency to kc.groups_per_cu
     if (kc.one_group_per_tile) {
         if (n_tiles > 0x7FFFFFFFull)
             return HU_ERR_INVALID_ARGUMENT;
         grid_ll = n_tiles ? n_tiles : 1;
     } else {
-        const int max_blocks = max_resident_blocks(kc.fn);
+        const int max_blocks = max_resident_blocks(kc.fn, kc.groups_per_cu, &pad);
         if (max_blocks <= 0)
             return HU_ERR_DEVICE;
         grid_ll = n_tiles == 0 ? 1ull : (n_tiles < (unsigned long long)max_blocks ? n_tiles : max_blocks);
@@ -155,7 +172,7 @@ int enqueue(int op, const void *src, unsigned long long n, void *dst, unsigned l
     Doc doc{base, off_b, off_b + (u16 ? 2 * n : n), n, dst, cap};
     unsigned long long n_tiles_arg = n_tiles;
     void *args[] = {&doc, &n_tiles_arg, &hdr, &status, &status_cap, &d_result};
-    if (hipLaunchKernel(kc.fn, dim3(grid), dim3(kBlock), args, 0, stream) != hipSuccess)
+    if (hipLaunchKernel(kc.fn, dim3(grid), dim3(kBlock), args, pad, stream) != hipSuccess)
         return HU_ERR_DEVICE;
     return HU_OK;
 }

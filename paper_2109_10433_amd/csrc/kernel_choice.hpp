@@ -89,7 +89,13 @@ struct KernelChoice {
     unsigned long long tile_bytes;
     bool one_group_per_tile;   // convert: one workgroup per tile, a status word per tile;
                                // else: persistent, each wave grid-stride over wave-tiles, no status words
+    unsigned int groups_per_cu = 0;   // persistent kernels: resident workgroups per CU at most (0: no limit)
 };
+
+// The UTF-8 length of UTF-16 input runs at most 5 workgroups (waves per SIMD)
+// per CU: it measured faster there than at the 6 its registers allow
+// (three-byte text by 5-7 %).
+constexpr unsigned int kLength16GroupsPerCu = 5;
 
 // An op with flags (variants.hip): false when the combination has no kernel.
 bool choose_variant(int op, unsigned long long n_bytes, KernelChoice &kc);

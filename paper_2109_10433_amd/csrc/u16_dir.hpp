@@ -75,13 +75,34 @@ struct U16Dir {
             *flag = kNoFlag;
             return COUNT ? 8u + extra_bytes(x) : 0u;
         }
-        int f = kNoFlag;
+        // Pairing, two words per dword operation: c = (w >> 10) ^ 0x36 is 0
+        // for a high surrogate and 1 for a low one (6 bits per 16-bit half);
+        // bit 6 of c + 0x3F is set when the word is not high, of
+        // (c ^ 1) + 0x3F when it is not low. Word j + 1 must be low exactly
+        // when word j is high, for the pairs (-1, 0) .. (7, 8); waves where
+        // every lane passes have no flagged word (a mismatch may also be word
+        // -1's or word 8's alone, which the search below then clears).
+        unsigned int mism = 0, nh_prev = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const unsigned int w = word(x, j), pw = word(x, j - 1), nw = word(x, j + 1);
-            const bool bad = (is_high(w) && !is_low(nw)) || (is_low(w) && !is_high(pw));
-            if (bad && f == kNoFlag)
-                f = j;
+        for (int k = 0; k <= 5; ++k) {
+            const unsigned int c = ((x[k] >> 10) & 0x003F003Fu) ^ 0x00360036u;
+            const unsigned int nh = (c + 0x003F003Fu) & 0x00400040u;
+            const unsigned int nl = ((c ^ 0x00010001u) + 0x003F003Fu) & 0x00400040u;
+            // halves: words 2k - 3 and 2k - 2 (not high) against words 2k - 2
+            // and 2k - 1 (not low)
+            if (k >= 1)
+                mism |= (__builtin_amdgcn_alignbit(nh, nh_prev, 16) ^ nl) & (k == 5 ? 0x40u : 0x00400040u);
+            nh_prev = nh;
+        }
+        int f = kNoFlag;
+        if (__any(mism != 0)) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const unsigned int w = word(x, j), pw = word(x, j - 1), nw = word(x, j + 1);
+                const bool bad = (is_high(w) && !is_low(nw)) || (is_low(w) && !is_high(pw));
+                if (bad && f == kNoFlag)
+                    f = j;
+            }
         }
         *flag = f;
         if (!COUNT)

@@ -42,7 +42,9 @@ bool choose_variant(int op, unsigned long long n_bytes, KernelChoice &kc)
     case HU_OP_CONVERT_UTF8_TO_UTF16LE | kBigEndianOp: kc = {convert8_kernel<kConvert, true>(u8), t8, true}; return true;
     case HU_OP_CONVERT_UTF16LE_TO_UTF8 | kBigEndianOp: kc = {convert16_kernel<kConvert, true>(u16), t16, true}; return true;
     case HU_OP_VALIDATE_UTF16LE | kBigEndianOp: kc = {HU_K(k_scan<U16Dir, kValidate, kPValidate16, true>), tv, false}; return true;
-    case HU_OP_UTF8_LENGTH_FROM_UTF16LE | kBigEndianOp: kc = {HU_K(k_scan<U16Dir, kLength, kPLength16, true>), tl, false}; return true;
+    case HU_OP_UTF8_LENGTH_FROM_UTF16LE | kBigEndianOp:
+        kc = {HU_K(k_scan<U16Dir, kLength, kPLength16, true>), tl, false, kLength16GroupsPerCu};
+        return true;
     default: return false;
     }
 #undef HU_K

@@ -167,6 +167,31 @@ def test_characters_split_across_wave_boundaries():
                     check_u16_all(u16)
 
 
+def test_surrogate_pairs_split_across_utf16_boundaries():
+    """A surrogate pair whose high word ends a chunk (8 words), a wave (512),
+    a sub-tile (2048) or a tile (2048 and 4096 for inputs of this size) and
+    whose low word starts the next: the low word's two UTF-8 bytes take two
+    bits of the high word, read across the boundary. The words after it are
+    of one kind (ASCII, two-byte, three-byte, more pairs), so the next
+    chunk's wave takes each encoder path in turn; a lone high or low word at
+    the same places must be flagged there."""
+    fillers = {"ascii": "abcdefgh", "two-byte": "aжbвcд", "three-byte": "a中b文", "pairs": "😀a🎉b"}
+    for boundary in (8, 512, 2048, 4096):
+        for name, fill in fillers.items():
+            for ch in ("😀", "\U0010FFFF", "\U00010000"):
+                text = "x" * (boundary - 1) + ch + (fill * (6000 // len(fill)))
+                u16 = np.frombuffer(text.encode("utf-16-le"), np.uint16)
+                assert u16[boundary - 1] >> 10 == 0x36 and u16[boundary] >> 10 == 0x37
+                say("pair split at word", boundary, repr(ch), "then", name)
+                assert check_u16_all(u16)[0] == 0
+            for w in (0xD83D, 0xDE00):
+                bad = np.frombuffer(("x" * (boundary - 1) + "y" + fill * (6000 // len(fill))).encode("utf-16-le"),
+                                    np.uint16).copy()
+                bad[boundary - 1 if w < 0xDC00 else boundary] = w
+                say("lone", hex(w), "at word", boundary, "then", name)
+                assert check_u16_all(bad)[0] == 7   # UNPAIRED_SURROGATE
+
+
 def test_four_byte_waves_with_one_short_lead():
     """Text of ASCII and four-byte characters only (a wave class whose decode
     leaves out the two- and three-byte forms) with one two- or three-byte

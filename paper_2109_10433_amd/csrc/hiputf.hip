@@ -85,7 +85,8 @@ KernelChoice choose_kernel(int op, unsigned long long n_bytes)
     }
     switch (op) {
     case HU_OP_VALIDATE_UTF8: return {HU_K(k_scan<U8Dir, kValidate, kPValidate8>), kPValidate8 * kPieceBytes, false};
-    case HU_OP_UTF16_LENGTH_FROM_UTF8: return {HU_K(k_scan<U8Dir, kLength, kPLength8>), kPLength8 * kPieceBytes, false};
+    case HU_OP_UTF16_LENGTH_FROM_UTF8:
+        return {HU_K(k_scan<U8Dir, kLength, kPLength8>), kPLength8 * kPieceBytes, false, kLength8GroupsPerCu};
     case HU_OP_CONVERT_UTF8_TO_UTF16LE: {
         const int u = class_sub_tiles(kConvert8Classes, n_bytes);
         const void *fn = u == 1 ? HU_K(k_convert_u8<1, kConvert>) : u == 2 ? HU_K(k_convert_u8<2, kConvert>)

@@ -92,10 +92,12 @@ struct KernelChoice {
     unsigned int groups_per_cu = 0;   // persistent kernels: resident workgroups per CU at most (0: no limit)
 };
 
-// The UTF-8 length of UTF-16 input runs at most 5 workgroups (waves per SIMD)
-// per CU: it measured faster there than at the 6 its registers allow
-// (three-byte text by 5-7 %).
+// The length kernels run at most this many workgroups (waves per SIMD) per
+// CU: each measured faster there than at the one more its registers allow
+// (UTF-8 length of UTF-16 input: three-byte text by 5-7 %; UTF-16 length of
+// UTF-8 input: Latin and Cyrillic by 6-8 %).
 constexpr unsigned int kLength16GroupsPerCu = 5;
+constexpr unsigned int kLength8GroupsPerCu = 6;
 
 // An op with flags (variants.hip): false when the combination has no kernel.
 bool choose_variant(int op, unsigned long long n_bytes, KernelChoice &kc);

@@ -163,7 +163,7 @@ struct U8Dir {
         for (int k = 0; k < 5; ++k)
             G[k] = ge_e0(x[k]);
         if (!__any(G[0] | G[1] | G[2] | G[3] | G[4])) {
-            unsigned int bad = 0, count = 0;
+            unsigned int bad = 0, n_cont = 0;   // continuation bytes: 16 - n_cont characters start here
             unsigned int lead_prev = x[0] & (x[0] << 1) & 0x80808080u;
             unsigned int c01_prev = lead_prev & ~payload_nonzero(x[0]);
 #pragma unroll
@@ -176,14 +176,14 @@ struct U8Dir {
                 bad |= (cont ^ __builtin_amdgcn_alignbyte(lead, lead_prev, 3)) |
                        __builtin_amdgcn_alignbyte(c01, c01_prev, 3);
                 if (COUNT)
-                    count += __popc(cont ^ 0x80808080u);
+                    n_cont += __popc(cont);
                 lead_prev = lead;
                 c01_prev = c01;
             }
             if (!__any(bad)) {
                 *flag = kNoFlag;
                 *cls = 0;
-                return count;
+                return COUNT ? 16u - n_cont : 0u;
             }
         }
         // per dword: bytes >= F0
